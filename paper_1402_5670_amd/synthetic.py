@@ -1,0 +1,106 @@
+"""Seeded synthetic inputs: piecewise-constant "cartoon" images and volumes
+plus Gaussian noise, the model class the paper's analysis is built on
+(Section 1: cartoon-like functions).  They stand in for the paper's natural
+test images and videos, which are not used.
+
+This module holds input generation only and none of the transform's
+arithmetic; both the HIP path's tests/benchmarks and the FP64 oracle's tests
+draw their inputs from here.
+
+Recipe (numpy PCG64 via default_rng(seed)):
+  2D: background ~ U[0,1]; n ~ U{8..16} shapes painted in order; each shape
+      is an ellipse (p = 1/2; centre ~ U over the image, semi-axes
+      ~ U[m/32, m/4] with m = min(H, W), angle ~ U[0, pi)) or a star-shaped
+      polygon (3..8 vertices at sorted U[0, 2 pi) angles, radii r*U[0.5, 1],
+      r ~ U[m/16, m/4]); intensity ~ U[0,1]; membership is tested at pixel
+      centres, so images are exactly piecewise constant.
+  3D: background ~ U[0,1]; n ~ U{10..20} ellipsoids, centre ~ U over the
+      volume, semi-axes ~ U[m/32, m/4], rotation = Q of a QR factorisation
+      of a standard normal 3x3 matrix; intensity ~ U[0,1].
+  noise: default_rng([seed, 1]).standard_normal(shape) * sigma (not clipped).
+"""
+import numpy as np
+
+
+def _inside_polygon(px, py, vx, vy):
+    """Even-odd rule for points (px, py) against the closed polygon (vx, vy)."""
+    inside = np.zeros(px.shape, dtype=bool)
+    n = len(vx)
+    for a in range(n):
+        b = (a + 1) % n
+        x1, y1, x2, y2 = vx[a], vy[a], vx[b], vy[b]
+        crosses = (y1 > py) != (y2 > py)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            xint = x1 + (py - y1) * (x2 - x1) / (y2 - y1)
+        inside ^= crosses & (px < xint)
+    return inside
+
+
+def cartoon2d(H, W, seed):
+    rng = np.random.default_rng(seed)
+    img = np.full((H, W), rng.uniform(0.0, 1.0))
+    yy, xx = np.meshgrid(np.arange(H) + 0.5, np.arange(W) + 0.5, indexing="ij")
+    m = float(min(H, W))
+    for _ in range(int(rng.integers(8, 17))):
+        val = rng.uniform(0.0, 1.0)
+        if rng.uniform() < 0.5:
+            cy, cx = rng.uniform(0, H), rng.uniform(0, W)
+            a, b = rng.uniform(m / 32, m / 4, size=2)
+            th = rng.uniform(0.0, np.pi)
+            dx, dy = xx - cx, yy - cy
+            u = dx * np.cos(th) + dy * np.sin(th)
+            v = -dx * np.sin(th) + dy * np.cos(th)
+            mask = (u / a) ** 2 + (v / b) ** 2 <= 1.0
+        else:
+            cy, cx = rng.uniform(0, H), rng.uniform(0, W)
+            nv = int(rng.integers(3, 9))
+            ang = np.sort(rng.uniform(0.0, 2 * np.pi, size=nv))
+            r = rng.uniform(m / 16, m / 4)
+            rad = r * rng.uniform(0.5, 1.0, size=nv)
+            mask = _inside_polygon(xx, yy, cx + rad * np.cos(ang), cy + rad * np.sin(ang))
+        img[mask] = val
+    return img
+
+
+def cartoon3d(D, H, W, seed):
+    rng = np.random.default_rng(seed)
+    vol = np.full((D, H, W), rng.uniform(0.0, 1.0))
+    zz, yy, xx = np.meshgrid(np.arange(D) + 0.5, np.arange(H) + 0.5, np.arange(W) + 0.5,
+                             indexing="ij")
+    m = float(min(D, H, W))
+    for _ in range(int(rng.integers(10, 21))):
+        val = rng.uniform(0.0, 1.0)
+        c = rng.uniform([0, 0, 0], [D, H, W])
+        ax = rng.uniform(m / 32, m / 4, size=3)
+        q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+        rel = np.stack([zz - c[0], yy - c[1], xx - c[2]], axis=-1) @ q
+        mask = np.sum((rel / ax) ** 2, axis=-1) <= 1.0
+        vol[mask] = val
+    return vol
+
+
+def noise(shape, seed, sigma):
+    return np.random.default_rng([seed, 1]).standard_normal(shape) * sigma
+
+
+def noisy_cartoon2d(H, W, seed, sigma):
+    clean = cartoon2d(H, W, seed)
+    return clean, clean + noise((H, W), seed, sigma)
+
+
+def noisy_cartoon3d(D, H, W, seed, sigma):
+    clean = cartoon3d(D, H, W, seed)
+    return clean, clean + noise((D, H, W), seed, sigma)
+
+
+# Workload recipes ----------------------------------------------------------
+
+def batch_sigmas(n):
+    """Noise levels (20, 30, 40)/255 cycled over a batch."""
+    return np.array([(20.0, 30.0, 40.0)[b % 3] / 255.0 for b in range(n)])
+
+
+def uneven_sizes(n=64, seed=4000, choices=(256, 384, 512, 1024)):
+    """Image sizes drawn uniformly from the given square sizes."""
+    idx = np.random.default_rng(seed).integers(0, len(choices), n)
+    return [int(choices[i]) for i in idx]
