@@ -1,0 +1,144 @@
+/*
+ * shearlet.h -- C ABI of the MI355X digital shearlet transform library
+ * (libshearlet.so).  Undecimated 2D and 3D digital shearlet transform with
+ * compactly supported shearlets as defined in "ShearLab 3D: Faithful Digital
+ * Shearlet Transforms based on Compactly Supported Shearlets" (Kutyniok,
+ * Lim, Reisenhofer, 2014).
+ *
+ * Conventions shared by every call
+ *   - Arrays are row-major with x1 fastest: a 2D signal is [H][W] = [N2][N1],
+ *     a 3D signal is [D][H][W] = [N3][N2][N1]; a batch adds a leading [B].
+ *   - The coefficient tensor is subband-major: [B][R][H][W] (2D) or
+ *     [B][R][D][H][W] (3D), each subband plane contiguous.  (The paper's
+ *     MATLAB example stores rows x cols x R with the subband index last,
+ *     Section 4.3; the layout here keeps each plane contiguous for streaming.)
+ *   - Subband order: index 0 is the lowpass; then for each scale j = 0..J-1
+ *     (coarse to fine) 2D: cone 1 for k = -L..L, cone 2 for k = -L+1..L-1
+ *     (k = -L..L with full_system), L = 2^{shear_levels[j]};
+ *     3D: pyramids 1, 2, 3, each with k1 outer and k2 inner in -L..L,
+ *     pyramid 2 skipping |k1| = L and pyramid 3 skipping |k1| = L or |k2| = L
+ *     unless full_system (Section 4.4).
+ *   - Pointers named *_dev are device pointers (hipMalloc'ed by the caller,
+ *     e.g. through PyTorch); pointers named *_host are host memory.  The
+ *     caller owns every buffer it passes; the library owns sl_system.
+ *   - stream is a hipStream_t passed as void* (NULL = the default stream).
+ *     GPU calls are asynchronous on that stream; argument errors are
+ *     returned synchronously, kernel faults surface at the caller's next
+ *     synchronisation.
+ *   - Every call returns an sl_status (0 = success) and never aborts;
+ *     sl_last_error() describes the last failure of the calling thread.
+ */
+#ifndef SHEARLET_H_
+#define SHEARLET_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SL_OK = 0,
+  SL_EINVAL = -1,        /* bad argument or configuration                   */
+  SL_ENOMEM = -2,        /* allocation failed or workspace too small        */
+  SL_EUNSUPPORTED = -3,  /* a dimension the device FFT does not support      */
+  SL_EILLCOND = -4,      /* min Psi_hat / max Psi_hat < 1e-6                */
+  SL_EHIP = -5           /* a HIP runtime call failed                       */
+};
+
+enum { SL_F32 = 0, SL_F16 = 1, SL_BF16 = 2 };   /* coefficient storage type */
+
+/* Shearlet system parameters (Algorithm 1's inputs, Section 4.1; the
+ * MATLAB interface of Section 4.3).                                          */
+typedef struct {
+  int ndim;                   /* 2 or 3                                        */
+  int64_t dims[3];            /* [H, W] or [D, H, W]; each 2^a or 3*2^a, 8..1024 */
+  int n_scales;               /* J >= 1 (nScales)                               */
+  const int *shear_levels;    /* host, length J, d_j in 0..4, coarse to fine    */
+  const double *qmf;          /* host, odd length, symmetric 1D lowpass h with
+                                 centre tap in the middle; NULL = the 9-tap
+                                 maximally flat h_ShearLab (Section 5.1)        */
+  int qmf_len;
+  const double *dir_filter;   /* host [dir_rows][dir_cols] taps of the fan
+                                 filter P, rows along x2, odd sizes, centred,
+                                 point-symmetric; NULL = the maximally flat
+                                 half-band fan D_2((cos 2pi eta2 -
+                                 cos 2pi eta1)/2) (eq. nonsep, Section 5.1)     */
+  int dir_rows, dir_cols;
+  int full_system;            /* 1 keeps the seam filters (Section 4.4)         */
+  int coeff_dtype;            /* SL_F32, SL_F16 or SL_BF16                      */
+} sl_config;
+
+/* One subband: cone 0 = lowpass; 1, 2 = 2D cones; 1, 2, 3 = 3D pyramids.     */
+typedef struct {
+  int cone, j, k1, k2;
+  double l2norm;              /* ||psi_i||_2 on the grid = sqrt(mean psi_hat^2) */
+  double l1norm;              /* ||psi_i||_1 on the grid (3D: Young bound)      */
+} sl_subband;
+
+typedef struct sl_system sl_system;
+
+/* ---- host-only calls (no GPU needed) ------------------------------------ */
+
+int sl_abi_version(void);
+const char *sl_last_error(void);
+
+/* Number of subbands R of a configuration (Sections 4.1 and 4.4).           */
+int sl_config_num_subbands(const sl_config *cfg, int *R_out);
+
+/* FP64 closed form of the frequency-domain filter bank on the DFT grid,
+ * evaluated on the host (Sections 3.2.2, 3.3.2, 3.4):
+ *   filters_host [R][dims...]  psi_hat_i (may be NULL),
+ *   dual_host    [dims...]     Psi_hat = sum_i psi_hat_i^2 (may be NULL),
+ *   subbands_host[R]           indices and norms (may be NULL).
+ * Returns SL_EILLCOND when Psi_hat is not bounded away from zero.           */
+int sl_build_filters_host(const sl_config *cfg, double *filters_host,
+                          double *dual_host, sl_subband *subbands_host);
+
+/* ---- system (host build + device upload) -------------------------------- */
+
+/* Build the filter bank on the host in FP64, round to FP32 and upload the
+ * tables plus FFT twiddles (computed in FP64, rounded to FP32) to the
+ * current HIP device.  *out is owned by the library.                        */
+int sl_build_system(const sl_config *cfg, sl_system **out);
+void sl_free_system(sl_system *s);
+int sl_system_num_subbands(const sl_system *s, int *R_out);
+int sl_system_subband(const sl_system *s, int i, sl_subband *out);
+
+/* Device bytes of workspace needed by forward/inverse/denoise for a batch.  */
+int sl_workspace_size(const sl_system *s, int batch, size_t *bytes_out);
+
+/* ---- transforms --------------------------------------------------------- */
+
+/* Forward transform (Algorithm 1): c_i = IDFT(psi_hat_i .* DFT(x)).
+ *   x_dev      [B][dims] float32
+ *   coeffs_dev [B][R][dims] of the system's coefficient type
+ *   scales_dev [B][R] float32 written for SL_F16/SL_BF16 storage (the stored
+ *              value is c / scale); may be NULL for SL_F32
+ *   workspace_dev of at least sl_workspace_size(s, B) bytes.                */
+int sl_forward(const sl_system *s, const float *x_dev, int batch, void *coeffs_dev,
+               float *scales_dev, void *workspace_dev, size_t workspace_bytes,
+               void *stream);
+
+/* Inverse transform (Algorithm 2 with the dual filters of eq. dual_filter):
+ *   x = IDFT( sum_i DFT(c_i) .* psi_hat_i / Psi_hat ).
+ * If sigma_dev is not NULL every detail coefficient is hard-thresholded on
+ * load (eq. hard_tresholding): kept iff |c| >= K[j] * sigma[b] * ||psi_i||_2,
+ * computed in float32 as (K[j] * sigma[b]) * l2norm_i; the lowpass is kept.
+ *   sigma_dev [B] float32 or NULL;  K_host [J] float32 (ignored if no sigma). */
+int sl_inverse(const sl_system *s, const void *coeffs_dev, const float *scales_dev,
+               int batch, const float *sigma_dev, const float *K_host, float *x_dev,
+               void *workspace_dev, size_t workspace_bytes, void *stream);
+
+/* Hard-threshold denoising T^-1 T_delta T x (Section 5.3): sl_forward into
+ * coeffs_dev (caller-provided, [B][R][dims]) then sl_inverse with sigma.     */
+int sl_denoise(const sl_system *s, const float *x_dev, int batch, const float *sigma_dev,
+               const float *K_host, void *coeffs_dev, float *scales_dev, float *out_dev,
+               void *workspace_dev, size_t workspace_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHEARLET_H_ */

@@ -1,0 +1,255 @@
+"""ctypes binding of libshearlet's C ABI (include/shearlet.h).
+
+Argument marshalling only: every step of the transform runs in the HIP
+library.  PyTorch provides device memory and the current stream; the
+library fails loudly (ImportError / RuntimeError) when it is missing or a
+call fails.  There is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libshearlet.so")
+
+SL_F32, SL_F16, SL_BF16 = 0, 1, 2
+_DTYPES = {"f32": SL_F32, "f16": SL_F16, "bf16": SL_BF16}
+_ERRORS = {-1: "SL_EINVAL", -2: "SL_ENOMEM", -3: "SL_EUNSUPPORTED", -4: "SL_EILLCOND",
+           -5: "SL_EHIP"}
+
+
+class ShearletError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int),
+        ("dims", ctypes.c_int64 * 3),
+        ("n_scales", ctypes.c_int),
+        ("shear_levels", ctypes.POINTER(ctypes.c_int)),
+        ("qmf", ctypes.POINTER(ctypes.c_double)),
+        ("qmf_len", ctypes.c_int),
+        ("dir_filter", ctypes.POINTER(ctypes.c_double)),
+        ("dir_rows", ctypes.c_int),
+        ("dir_cols", ctypes.c_int),
+        ("full_system", ctypes.c_int),
+        ("coeff_dtype", ctypes.c_int),
+    ]
+
+
+class Subband(ctypes.Structure):
+    _fields_ = [("cone", ctypes.c_int), ("j", ctypes.c_int), ("k1", ctypes.c_int),
+                ("k2", ctypes.c_int), ("l2norm", ctypes.c_double), ("l1norm", ctypes.c_double)]
+
+
+_lib = None
+
+_SIGS = {
+    "sl_abi_version": ([], ctypes.c_int),
+    "sl_last_error": ([], ctypes.c_char_p),
+    "sl_config_num_subbands": ([ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "sl_build_filters_host": ([ctypes.POINTER(Config), ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_void_p], ctypes.c_int),
+    "sl_build_system": ([ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "sl_free_system": ([ctypes.c_void_p], None),
+    "sl_system_num_subbands": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "sl_system_subband": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Subband)], ctypes.c_int),
+    "sl_workspace_size": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
+                          ctypes.c_int),
+    "sl_forward": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
+                   ctypes.c_int),
+    "sl_inverse": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                    ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+    "sl_denoise": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                    ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+}
+
+
+def lib():
+    """Load libshearlet.so (raises ImportError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run python -m paper_1402_5670_amd.build")
+        h = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(h, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = h
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def check(rc):
+    if rc != 0:
+        raise ShearletError(rc, lib().sl_last_error().decode())
+
+
+class _Cfg:
+    """Keeps the ctypes arrays referenced by a Config alive."""
+
+    def __init__(self, dims, n_scales, shear_levels, full_system=False, dtype="f32", qmf=None,
+                 dir_filter=None):
+        self.levels = (ctypes.c_int * len(shear_levels))(*[int(v) for v in shear_levels])
+        c = Config()
+        c.ndim = len(dims)
+        for i, d in enumerate(dims):
+            c.dims[i] = int(d)
+        c.n_scales = int(n_scales)
+        c.shear_levels = self.levels
+        if qmf is not None:
+            self.qmf = np.ascontiguousarray(qmf, dtype=np.float64)
+            c.qmf = self.qmf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            c.qmf_len = len(self.qmf)
+        if dir_filter is not None:
+            self.dirf = np.ascontiguousarray(dir_filter, dtype=np.float64)
+            c.dir_filter = self.dirf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            c.dir_rows, c.dir_cols = self.dirf.shape
+        c.full_system = int(bool(full_system))
+        c.coeff_dtype = _DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+        self.c = c
+
+
+def num_subbands(dims, n_scales, shear_levels, full_system=False):
+    cfg = _Cfg(dims, n_scales, shear_levels, full_system)
+    R = ctypes.c_int()
+    check(lib().sl_config_num_subbands(ctypes.byref(cfg.c), ctypes.byref(R)))
+    return R.value
+
+
+def build_filters_host(dims, n_scales, shear_levels, full_system=False, qmf=None,
+                       dir_filter=None):
+    """Host FP64 closed-form filters: (filters [R, *dims], Psi_hat, subbands)."""
+    cfg = _Cfg(dims, n_scales, shear_levels, full_system, "f32", qmf, dir_filter)
+    R = ctypes.c_int()
+    check(lib().sl_config_num_subbands(ctypes.byref(cfg.c), ctypes.byref(R)))
+    filt = np.zeros((R.value, *dims), dtype=np.float64)
+    dual = np.zeros(dims, dtype=np.float64)
+    subs = (Subband * R.value)()
+    check(lib().sl_build_filters_host(ctypes.byref(cfg.c), filt.ctypes.data, dual.ctypes.data,
+                                      ctypes.cast(subs, ctypes.c_void_p)))
+    return filt, dual, [(s.cone, s.j, s.k1, s.k2, s.l2norm, s.l1norm) for s in subs]
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class System:
+    """A shearlet system resident on the current HIP device."""
+
+    def __init__(self, dims, n_scales, shear_levels, full_system=False, dtype="f32", qmf=None,
+                 dir_filter=None):
+        self.dims = tuple(int(d) for d in dims)
+        self.n_scales = int(n_scales)
+        self.shear_levels = tuple(int(v) for v in shear_levels)
+        self.dtype = dtype
+        self._cfg = _Cfg(dims, n_scales, shear_levels, full_system, dtype, qmf, dir_filter)
+        h = ctypes.c_void_p()
+        check(lib().sl_build_system(ctypes.byref(self._cfg.c), ctypes.byref(h)))
+        self._h = h
+        R = ctypes.c_int()
+        check(lib().sl_system_num_subbands(h, ctypes.byref(R)))
+        self.R = R.value
+        self.subbands = []
+        for i in range(self.R):
+            s = Subband()
+            check(lib().sl_system_subband(h, i, ctypes.byref(s)))
+            self.subbands.append((s.cone, s.j, s.k1, s.k2, s.l2norm, s.l1norm))
+        self._ws = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.sl_free_system(h)
+            self._h = None
+
+    @property
+    def l2norms(self):
+        return np.array([s[4] for s in self.subbands])
+
+    @property
+    def torch_coeff_dtype(self):
+        import torch
+        return {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[self.dtype]
+
+    def workspace_bytes(self, batch):
+        n = ctypes.c_size_t()
+        check(lib().sl_workspace_size(self._h, int(batch), ctypes.byref(n)))
+        return n.value
+
+    def workspace(self, batch, device):
+        import torch
+        n = self.workspace_bytes(batch)
+        ws = self._ws.get(str(device))
+        if ws is None or ws.numel() < n:
+            ws = torch.empty(n, dtype=torch.uint8, device=device)
+            self._ws[str(device)] = ws
+        return ws
+
+    def alloc_coeffs(self, batch, device):
+        import torch
+        c = torch.empty((batch, self.R, *self.dims), dtype=self.torch_coeff_dtype, device=device)
+        s = torch.empty((batch, self.R), dtype=torch.float32, device=device)
+        return c, s
+
+    def _check_x(self, x):
+        import torch
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32
+                and x.is_contiguous() and tuple(x.shape[1:]) == self.dims):
+            raise ValueError(f"expected a contiguous float32 CUDA tensor [B, {self.dims}]")
+
+    def forward(self, x, coeffs=None, scales=None, workspace=None):
+        self._check_x(x)
+        B = x.shape[0]
+        if coeffs is None:
+            coeffs, scales = self.alloc_coeffs(B, x.device)
+        ws = workspace if workspace is not None else self.workspace(B, x.device)
+        check(lib().sl_forward(self._h, _ptr(x), B, _ptr(coeffs), _ptr(scales), _ptr(ws),
+                               ws.numel(), _stream()))
+        return coeffs, scales
+
+    def inverse(self, coeffs, scales=None, sigma=None, K=None, out=None, workspace=None):
+        import torch
+        B = coeffs.shape[0]
+        if out is None:
+            out = torch.empty((B, *self.dims), dtype=torch.float32, device=coeffs.device)
+        ws = workspace if workspace is not None else self.workspace(B, coeffs.device)
+        Kh = None
+        if sigma is not None:
+            Kh = (ctypes.c_float * len(K))(*[float(k) for k in K])
+        check(lib().sl_inverse(self._h, _ptr(coeffs), _ptr(scales), B, _ptr(sigma),
+                               ctypes.cast(Kh, ctypes.c_void_p) if Kh is not None else None,
+                               _ptr(out), _ptr(ws), ws.numel(), _stream()))
+        return out
+
+    def denoise(self, x, sigma, K, coeffs=None, scales=None, out=None, workspace=None):
+        import torch
+        self._check_x(x)
+        B = x.shape[0]
+        if coeffs is None:
+            coeffs, scales = self.alloc_coeffs(B, x.device)
+        if out is None:
+            out = torch.empty_like(x)
+        ws = workspace if workspace is not None else self.workspace(B, x.device)
+        Kh = (ctypes.c_float * len(K))(*[float(k) for k in K])
+        check(lib().sl_denoise(self._h, _ptr(x), B, _ptr(sigma), ctypes.cast(Kh, ctypes.c_void_p),
+                               _ptr(coeffs), _ptr(scales), _ptr(out), _ptr(ws), ws.numel(),
+                               _stream()))
+        return out

@@ -1,0 +1,349 @@
+// C ABI of libshearlet (declared in include/shearlet.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/shearlet.h"
+#include "dispatch.hpp"
+#include "host_filters.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return SL_EHIP;
+}
+
+size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct sl_system {
+  slh::Config cfg;
+  std::vector<slh::Subband> subs;
+  std::vector<double> l2, l1;
+  int R = 0;
+  int device = 0;
+  size_t chunk_cap = 0;
+  float *d_filt = nullptr;    // 2D: [R][H][W]
+  float *d_psi = nullptr;     // Psi_hat on the grid
+  float *d_l2 = nullptr, *d_l1 = nullptr;
+  int *d_jof = nullptr;
+  std::map<int, float2 *> d_tw;
+  std::vector<void *> allocs;
+};
+
+namespace {
+
+template <class T>
+int dev_upload(sl_system *s, const std::vector<T> &host, T **out) {
+  void *p = nullptr;
+  size_t bytes = std::max<size_t>(sizeof(T), host.size() * sizeof(T));
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+  s->allocs.push_back(p);
+  if (!host.empty()) {
+    e = hipMemcpy(p, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  }
+  *out = (T *)p;
+  return SL_OK;
+}
+
+// exp(-2 pi i m / N), m = 0..N-1, computed in FP64 and rounded to FP32
+std::vector<float2> twiddles(int N) {
+  std::vector<float2> t(N);
+  for (int m = 0; m < N; ++m) {
+    long double a = -2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)N;
+    t[m].x = (float)(double)std::cos(a);
+    t[m].y = (float)(double)std::sin(a);
+  }
+  return t;
+}
+
+void chunk_plan(const sl_system *s, int B, int &nb, int &np) {
+  const int P = (s->R + 1) / 2;
+  const size_t plane = 8ull * (size_t)s->cfg.npix();
+  const size_t cap = s->chunk_cap;
+  if ((size_t)B * P * plane <= cap) {
+    nb = B;
+    np = P;
+  } else if ((size_t)B * plane <= cap) {
+    nb = B;
+    np = (int)std::max<size_t>(1, cap / ((size_t)B * plane));
+  } else {
+    nb = (int)std::max<size_t>(1, cap / plane);
+    np = 1;
+  }
+}
+
+struct Layout {
+  size_t off_F, off_chunk, off_xmax, total;
+};
+
+Layout layout(const sl_system *s, int B) {
+  int nb, np;
+  chunk_plan(s, B, nb, np);
+  const size_t plane = 8ull * (size_t)s->cfg.npix();
+  Layout L;
+  L.off_F = 0;
+  L.off_chunk = align_up(plane * B);
+  L.off_xmax = align_up(L.off_chunk + plane * (size_t)nb * np);
+  L.total = align_up(L.off_xmax + 4ull * B);
+  return L;
+}
+
+sl::Sys2D view2d(const sl_system *s) {
+  sl::Sys2D v;
+  v.H = (int)s->cfg.dims[0];
+  v.W = (int)s->cfg.dims[1];
+  v.R = s->R;
+  v.dtype = s->cfg.dtype;
+  v.filt = s->d_filt;
+  v.psi = s->d_psi;
+  v.l1 = s->d_l1;
+  v.twH = s->d_tw.at(v.H);
+  v.twW = s->d_tw.at(v.W);
+  return v;
+}
+
+int check_call(const sl_system *s, int batch, const void *a, const void *b, void *ws,
+               size_t ws_bytes) {
+  if (!s) return fail(SL_EINVAL, "system is NULL");
+  if (batch < 1) return fail(SL_EINVAL, "batch must be >= 1");
+  if (!a || !b || !ws) return fail(SL_EINVAL, "NULL buffer");
+  if (s->cfg.ndim != 2) return fail(SL_EUNSUPPORTED, "3D transforms are not available");
+  size_t need = layout(s, batch).total;
+  if (ws_bytes < need)
+    return fail(SL_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != s->device)
+    return fail(SL_EINVAL, "the current HIP device is not the system's device");
+  return SL_OK;
+}
+
+#define SL_TRY(expr)                                   \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr);  \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int sl_abi_version(void) { return 1; }
+
+const char *sl_last_error(void) { return g_err.c_str(); }
+
+int sl_config_num_subbands(const sl_config *cfg, int *R_out) {
+  slh::Config c;
+  std::string err;
+  int rc = slh::parse_config(cfg, c, err);
+  if (rc != SL_OK) return fail(rc, err);
+  if (!R_out) return fail(SL_EINVAL, "R_out is NULL");
+  *R_out = (int)slh::enumerate_subbands(c).size();
+  return SL_OK;
+}
+
+int sl_build_filters_host(const sl_config *cfg, double *filters_host, double *dual_host,
+                          sl_subband *subbands_host) {
+  slh::Config c;
+  std::string err;
+  int rc = slh::parse_config(cfg, c, err);
+  if (rc != SL_OK) return fail(rc, err);
+  slh::Bank bank;
+  rc = slh::build_bank(c, bank, filters_host, err);
+  if (dual_host) std::copy(bank.dual.begin(), bank.dual.end(), dual_host);
+  if (subbands_host)
+    for (size_t i = 0; i < bank.subbands.size(); ++i) {
+      const auto &s = bank.subbands[i];
+      subbands_host[i] = {s.cone, s.j, s.k1, s.k2, bank.l2[i], bank.l1[i]};
+    }
+  if (rc != SL_OK) return fail(rc, err);
+  return SL_OK;
+}
+
+int sl_build_system(const sl_config *cfg, sl_system **out) {
+  if (!out) return fail(SL_EINVAL, "out is NULL");
+  *out = nullptr;
+  auto *s = new sl_system();
+  std::string err;
+  int rc = slh::parse_config(cfg, s->cfg, err);
+  if (rc != SL_OK) {
+    delete s;
+    return fail(rc, err);
+  }
+  if (s->cfg.ndim != 2) {
+    delete s;
+    return fail(SL_EUNSUPPORTED, "3D systems are not available");
+  }
+  const int64_t npix = s->cfg.npix();
+  int R = 0;
+  sl_config_num_subbands(cfg, &R);
+  std::vector<double> filt64((size_t)R * npix);
+  slh::Bank bank;
+  rc = slh::build_bank(s->cfg, bank, filt64.data(), err);
+  if (rc != SL_OK) {
+    delete s;
+    return fail(rc, err);
+  }
+  s->subs = bank.subbands;
+  s->R = R;
+  s->l2 = bank.l2;
+  s->l1 = bank.l1;
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return fail(SL_EHIP, "no HIP device");
+  }
+  const char *cap_env = std::getenv("SL_CHUNK_MB");
+  s->chunk_cap = (size_t)(cap_env ? std::max(1, std::atoi(cap_env)) : 128) << 20;
+  std::vector<float> f32(filt64.size());
+  for (size_t i = 0; i < f32.size(); ++i) f32[i] = (float)filt64[i];
+  std::vector<float> psi32(bank.dual.size());
+  for (size_t i = 0; i < psi32.size(); ++i) psi32[i] = (float)bank.dual[i];
+  std::vector<float> l2f(R), l1f(R);
+  std::vector<int> jof(R);
+  for (int i = 0; i < R; ++i) {
+    l2f[i] = (float)bank.l2[i];
+    // the FP16 scale needs an upper bound: round the l1 norm up
+    l1f[i] = std::nextafter((float)bank.l1[i], INFINITY);
+    jof[i] = bank.subbands[i].cone == 0 ? -1 : bank.subbands[i].j;
+  }
+  if ((rc = dev_upload(s, f32, &s->d_filt)) || (rc = dev_upload(s, psi32, &s->d_psi)) ||
+      (rc = dev_upload(s, l2f, &s->d_l2)) || (rc = dev_upload(s, l1f, &s->d_l1)) ||
+      (rc = dev_upload(s, jof, &s->d_jof))) {
+    sl_free_system(s);
+    return rc;
+  }
+  for (int a = 0; a < s->cfg.ndim; ++a) {
+    int N = (int)s->cfg.dims[a];
+    if (s->d_tw.count(N)) continue;
+    float2 *p = nullptr;
+    if ((rc = dev_upload(s, twiddles(N), &p))) {
+      sl_free_system(s);
+      return rc;
+    }
+    s->d_tw[N] = p;
+  }
+  *out = s;
+  return SL_OK;
+}
+
+void sl_free_system(sl_system *s) {
+  if (!s) return;
+  for (void *p : s->allocs) (void)hipFree(p);
+  delete s;
+}
+
+int sl_system_num_subbands(const sl_system *s, int *R_out) {
+  if (!s || !R_out) return fail(SL_EINVAL, "NULL argument");
+  *R_out = s->R;
+  return SL_OK;
+}
+
+int sl_system_subband(const sl_system *s, int i, sl_subband *out) {
+  if (!s || !out) return fail(SL_EINVAL, "NULL argument");
+  if (i < 0 || i >= s->R) return fail(SL_EINVAL, "subband index out of range");
+  const auto &b = s->subs[i];
+  *out = {b.cone, b.j, b.k1, b.k2, s->l2[i], s->l1[i]};
+  return SL_OK;
+}
+
+int sl_workspace_size(const sl_system *s, int batch, size_t *bytes_out) {
+  if (!s || !bytes_out) return fail(SL_EINVAL, "NULL argument");
+  if (batch < 1) return fail(SL_EINVAL, "batch must be >= 1");
+  *bytes_out = layout(s, batch).total;
+  return SL_OK;
+}
+
+int sl_forward(const sl_system *s, const float *x_dev, int batch, void *coeffs_dev,
+               float *scales_dev, void *workspace_dev, size_t workspace_bytes, void *stream) {
+  int rc = check_call(s, batch, x_dev, coeffs_dev, workspace_dev, workspace_bytes);
+  if (rc) return rc;
+  const bool scaled = s->cfg.dtype != SL_F32;
+  if (scaled && !scales_dev) return fail(SL_EINVAL, "scales_dev is required for F16/BF16 storage");
+  hipStream_t st = (hipStream_t)stream;
+  const sl::Sys2D v = view2d(s);
+  const Layout L = layout(s, batch);
+  char *ws = (char *)workspace_dev;
+  float2 *F = (float2 *)(ws + L.off_F);
+  float2 *T = (float2 *)(ws + L.off_chunk);
+  unsigned *xmax = (unsigned *)(ws + L.off_xmax);
+  if (scaled) SL_TRY(sl::launch_zero_u32(xmax, batch, st));
+  SL_TRY(sl::launch_rows_real_fft(v, x_dev, F, scaled ? xmax : nullptr, batch, st));
+  SL_TRY(sl::launch_cols_fft(v, F, F, batch, st));
+  if (scaled) SL_TRY(sl::launch_scales(v, xmax, scales_dev, batch, st));
+  int nb, np;
+  chunk_plan(s, batch, nb, np);
+  const int P = (s->R + 1) / 2;
+  for (int b0 = 0; b0 < batch; b0 += nb)
+    for (int p0 = 0; p0 < P; p0 += np) {
+      sl::Chunk c{b0, std::min(nb, batch - b0), p0, std::min(np, P - p0)};
+      SL_TRY(sl::launch_cols_filter_ifft(v, F, T, c, st));
+      SL_TRY(sl::launch_rows_coef(v, T, coeffs_dev, scales_dev, c, st));
+    }
+  return SL_OK;
+}
+
+int sl_inverse(const sl_system *s, const void *coeffs_dev, const float *scales_dev, int batch,
+               const float *sigma_dev, const float *K_host, float *x_dev, void *workspace_dev,
+               size_t workspace_bytes, void *stream) {
+  int rc = check_call(s, batch, coeffs_dev, x_dev, workspace_dev, workspace_bytes);
+  if (rc) return rc;
+  const bool scaled = s->cfg.dtype != SL_F32;
+  if (scaled && !scales_dev) return fail(SL_EINVAL, "scales_dev is required for F16/BF16 storage");
+  sl::ThrArgs thr{};
+  thr.sigma = sigma_dev;
+  thr.l2 = s->d_l2;
+  thr.jof = s->d_jof;
+  if (sigma_dev) {
+    if (!K_host) return fail(SL_EINVAL, "K_host is required with sigma_dev");
+    if (s->cfg.J > sl::kMaxScales) return fail(SL_EUNSUPPORTED, "too many scales");
+    for (int j = 0; j < s->cfg.J; ++j) thr.K[j] = K_host[j];
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const sl::Sys2D v = view2d(s);
+  const Layout L = layout(s, batch);
+  char *ws = (char *)workspace_dev;
+  float2 *ACC = (float2 *)(ws + L.off_F);
+  float2 *U = (float2 *)(ws + L.off_chunk);
+  int nb, np;
+  chunk_plan(s, batch, nb, np);
+  const int P = (s->R + 1) / 2;
+  for (int b0 = 0; b0 < batch; b0 += nb)
+    for (int p0 = 0; p0 < P; p0 += np) {
+      sl::Chunk c{b0, std::min(nb, batch - b0), p0, std::min(np, P - p0)};
+      SL_TRY(sl::launch_rows_coef_fft(v, coeffs_dev, scales_dev, U, c, thr, st));
+      SL_TRY(sl::launch_cols_fft_acc(v, U, ACC, c, p0 == 0, p0 + c.np == P, st));
+    }
+  SL_TRY(sl::launch_rows_real_ifft(v, ACC, x_dev, batch, st));
+  return SL_OK;
+}
+
+int sl_denoise(const sl_system *s, const float *x_dev, int batch, const float *sigma_dev,
+               const float *K_host, void *coeffs_dev, float *scales_dev, float *out_dev,
+               void *workspace_dev, size_t workspace_bytes, void *stream) {
+  if (!sigma_dev || !K_host) return fail(SL_EINVAL, "sigma_dev and K_host are required");
+  int rc = sl_forward(s, x_dev, batch, coeffs_dev, scales_dev, workspace_dev, workspace_bytes,
+                      stream);
+  if (rc) return rc;
+  return sl_inverse(s, coeffs_dev, scales_dev, batch, sigma_dev, K_host, out_dev, workspace_dev,
+                    workspace_bytes, stream);
+}
+
+}  // extern "C"

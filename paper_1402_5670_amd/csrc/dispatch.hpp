@@ -1,0 +1,65 @@
+// Host-side launchers of the device passes (internal to libshearlet).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace sl {
+
+constexpr int kMaxScales = 8;
+
+// Hard-threshold parameters fused into the first inverse pass.
+struct ThrArgs {
+  const float *sigma;   // [B] device, or null = no thresholding
+  const float *l2;      // [R] device ||psi_i||_2 (float32)
+  const int *jof;       // [R] device scale index (-1 = lowpass)
+  float K[kMaxScales];
+};
+
+// Per-call view of the 2D system tables.
+struct Sys2D {
+  int H, W, R, dtype;
+  const float *filt;        // [R][H][W]
+  const float *psi;         // [H][W]  Psi_hat
+  const float *l1;          // [R]
+  const float2 *twH, *twW;  // twiddles exp(-2 pi i m / N), N = H and N = W
+};
+
+// Chunk of (images, subband pairs) processed between two passes.
+struct Chunk {
+  int b0, nb, p0, np;
+};
+
+bool lines_supported(int n);
+
+// Forward passes --------------------------------------------------------------
+// x [B][H][W] real -> A [B][H][W] complex (row DFT); xmax[b] = max |x_b| bits
+hipError_t launch_rows_real_fft(const Sys2D &s, const float *x, float2 *A, unsigned *xmax, int B,
+                                hipStream_t st);
+// A -> F (column DFT)
+hipError_t launch_cols_fft(const Sys2D &s, const float2 *A, float2 *F, int B, hipStream_t st);
+// F, filters -> T[chunk] (filter pair multiply + column inverse DFT)
+hipError_t launch_cols_filter_ifft(const Sys2D &s, const float2 *F, float2 *T, Chunk c,
+                                   hipStream_t st);
+// T[chunk] -> coefficients (row inverse DFT, pair split, storage encode)
+hipError_t launch_rows_coef(const Sys2D &s, const float2 *T, void *coef, const float *scales,
+                            Chunk c, hipStream_t st);
+// scales[b][i] from xmax and l1 norms (F16 / BF16 storage)
+hipError_t launch_scales(const Sys2D &s, const unsigned *xmax, float *scales, int B,
+                         hipStream_t st);
+hipError_t launch_zero_u32(unsigned *p, int n, hipStream_t st);
+
+// Inverse passes --------------------------------------------------------------
+// coefficients -> U[chunk] (decode, threshold, pair pack, row DFT)
+hipError_t launch_rows_coef_fft(const Sys2D &s, const void *coef, const float *scales, float2 *U,
+                                Chunk c, const ThrArgs &thr, hipStream_t st);
+// U[chunk] -> ACC (column DFT, multiply by the filter pair, sum over pairs);
+// the last chunk divides by Psi_hat and applies the column inverse DFT.
+hipError_t launch_cols_fft_acc(const Sys2D &s, const float2 *U, float2 *ACC, Chunk c, bool first,
+                               bool last, hipStream_t st);
+// ACC -> x (row inverse DFT, real part, 1/(HW))
+hipError_t launch_rows_real_ifft(const Sys2D &s, const float2 *V, float *x, int B, hipStream_t st);
+
+}  // namespace sl

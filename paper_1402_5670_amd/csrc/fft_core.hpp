@@ -1,0 +1,209 @@
+// Stockham FFT building blocks for CDNA4 (gfx950), FP32 arithmetic with
+// twiddles tabulated on the host in FP64 and rounded to FP32.
+//
+// A length-N line is processed by NT threads, each owning E = N / NT
+// complex values.  On entry and on exit thread t holds the element at line
+// position t + e * NT in register v[e] (e = 0..E-1), so a pointwise operation
+// between a forward and an inverse transform needs no data movement.  The
+// first radix stage reads directly from registers, the last stage writes
+// directly to registers; stages in between exchange through LDS.
+//
+// Stockham stage of radix r after a sub-transform length p (product of the
+// earlier radices), for butterfly i in [0, N/r):
+//     k = i mod p,   x_q = in[i + q N/r] * W_N^{q k N/(p r)},
+//     y = DFT_r(x),  out[(i - k) r + k + q p] = y_q,
+// with W_N = exp(-2 pi i / N) (conjugated for the inverse transform).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace sl {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulconj(float2 a, float2 b) {  // a * conj(b)
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+// multiply by -i (forward direction) or +i (inverse direction)
+template <bool INV>
+__device__ __forceinline__ float2 rot90(float2 a) {
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft2(float2 *x) {
+  float2 a = x[0], b = x[1];
+  x[0] = cadd(a, b);
+  x[1] = csub(a, b);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft3(float2 *x) {
+  const float s3 = 0.86602540378443864676f;   // sqrt(3)/2
+  float2 s = cadd(x[1], x[2]);
+  float2 d = csub(x[1], x[2]);
+  float2 m = make_float2(x[0].x - 0.5f * s.x, x[0].y - 0.5f * s.y);
+  float2 rd = rot90<INV>(d);                   // -i d (forward)
+  x[0] = cadd(x[0], s);
+  x[1] = make_float2(m.x + s3 * rd.x, m.y + s3 * rd.y);
+  x[2] = make_float2(m.x - s3 * rd.x, m.y - s3 * rd.y);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2 *x) {
+  float2 t0 = cadd(x[0], x[2]), t1 = csub(x[0], x[2]);
+  float2 t2 = cadd(x[1], x[3]), t3 = rot90<INV>(csub(x[1], x[3]));
+  x[0] = cadd(t0, t2);
+  x[2] = csub(t0, t2);
+  x[1] = cadd(t1, t3);
+  x[3] = csub(t1, t3);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft8(float2 *x) {
+  const float r = 0.70710678118654752440f;
+  float2 b0 = cadd(x[0], x[4]), b4 = csub(x[0], x[4]);
+  float2 b1 = cadd(x[1], x[5]), b5 = csub(x[1], x[5]);
+  float2 b2 = cadd(x[2], x[6]), b6 = csub(x[2], x[6]);
+  float2 b3 = cadd(x[3], x[7]), b7 = csub(x[3], x[7]);
+  // odd half twiddles W8^1, W8^2, W8^3 (conjugated for the inverse)
+  if (INV) {
+    b5 = make_float2(r * (b5.x - b5.y), r * (b5.x + b5.y));
+    b7 = make_float2(-r * (b7.x + b7.y), r * (b7.x - b7.y));
+  } else {
+    b5 = make_float2(r * (b5.x + b5.y), r * (b5.y - b5.x));
+    b7 = make_float2(r * (b7.y - b7.x), -r * (b7.x + b7.y));
+  }
+  b6 = rot90<INV>(b6);
+  float2 e[4] = {b0, b1, b2, b3};
+  float2 o[4] = {b4, b5, b6, b7};
+  dft4<INV>(e);
+  dft4<INV>(o);
+  x[0] = e[0]; x[2] = e[1]; x[4] = e[2]; x[6] = e[3];
+  x[1] = o[0]; x[3] = o[1]; x[5] = o[2]; x[7] = o[3];
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft_r(float2 *x) {
+  if constexpr (R == 2) dft2<INV>(x);
+  else if constexpr (R == 3) dft3<INV>(x);
+  else if constexpr (R == 4) dft4<INV>(x);
+  else dft8<INV>(x);
+}
+
+// ---------------------------------------------------------------------------
+// compile-time radix plans: 8s first, then a 4 or 2, then 3s
+// ---------------------------------------------------------------------------
+template <int N>
+struct Plan {
+  static constexpr int count3() { int n = N, c = 0; while (n % 3 == 0) { n /= 3; ++c; } return c; }
+  static constexpr int pow2() { int n = N; while (n % 3 == 0) n /= 3; return n; }
+  static constexpr int log2p() { int n = pow2(), c = 0; while (n > 1) { n /= 2; ++c; } return c; }
+  static constexpr int n8 = log2p() / 3;
+  static constexpr int rem2 = log2p() % 3;              // 0, 1 (radix 2) or 2 (radix 4)
+  static constexpr int n3 = count3();
+  static constexpr int S = n8 + (rem2 ? 1 : 0) + n3;
+  static constexpr int radix(int s) {
+    return s < n8 ? 8 : (rem2 && s == n8) ? (rem2 == 1 ? 2 : 4) : 3;
+  }
+  static constexpr int lcm_radix() {
+    int l = 1;
+    for (int s = 0; s < S; ++s) {
+      int r = radix(s);
+      int a = l, b = r;
+      while (b) { int t = a % b; a = b; b = t; }
+      l = l / a * r;
+    }
+    return l;
+  }
+  static constexpr int E = lcm_radix();     // values per thread
+  static constexpr int NT = N / E;          // threads per line
+  static constexpr int pbefore(int s) { int p = 1; for (int q = 0; q < s; ++q) p *= radix(q); return p; }
+  static_assert(pow2() * (N / pow2()) == N, "bad size");
+};
+
+// LDS addressing of line m: element n at base[n * LN + m * LM].
+struct LdsLine {
+  float2 *base;
+  int stride_n;
+  __device__ __forceinline__ float2 &operator[](int n) const { return base[n * stride_n]; }
+};
+
+template <int N, int S_, bool INV>
+__device__ __forceinline__ void fft_stage(float2 (&v)[Plan<N>::E], int t, const LdsLine &lds,
+                                          const float2 *__restrict__ tw) {
+  using PL = Plan<N>;
+  constexpr int E = PL::E, NT = PL::NT;
+  constexpr int r = PL::radix(S_);
+  constexpr int p = PL::pbefore(S_);
+  constexpr int NB = E / r;          // butterflies per thread
+  constexpr int stride = N / r;
+  float2 x[NB][r];
+  if constexpr (S_ == 0) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int q = 0; q < r; ++q) x[b][q] = v[b + q * NB];
+  } else {
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      int i = t + b * NT;
+#pragma unroll
+      for (int q = 0; q < r; ++q) x[b][q] = lds[i + q * stride];
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    int i = t + b * NT;
+    if constexpr (p > 1) {
+      int k = i % p;
+#pragma unroll
+      for (int q = 1; q < r; ++q) {
+        float2 w = tw[q * k * (N / (p * r))];
+        x[b][q] = INV ? cmulconj(x[b][q], w) : cmul(x[b][q], w);
+      }
+    }
+    dft_r<r, INV>(x[b]);
+  }
+  if constexpr (S_ == PL::S - 1) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int q = 0; q < r; ++q) v[b + q * NB] = x[b][q];
+  } else {
+    if constexpr (S_ > 0) __syncthreads();
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      int i = t + b * NT;
+      int k = i % p;
+      int j = (i - k) * r + k;
+#pragma unroll
+      for (int q = 0; q < r; ++q) lds[j + q * p] = x[b][q];
+    }
+  }
+}
+
+template <int N, bool INV, int S_ = 0>
+__device__ __forceinline__ void fft_stages(float2 (&v)[Plan<N>::E], int t, const LdsLine &lds,
+                                           const float2 *__restrict__ tw) {
+  if constexpr (S_ < Plan<N>::S) {
+    fft_stage<N, S_, INV>(v, t, lds, tw);
+    fft_stages<N, INV, S_ + 1>(v, t, lds, tw);
+  }
+}
+
+// Full length-N FFT of one line held in registers (see file comment).  The
+// leading barrier makes it safe to call repeatedly on the same LDS buffer.
+// A single-stage plan never touches LDS.
+template <int N, bool INV>
+__device__ __forceinline__ void fft_line(float2 (&v)[Plan<N>::E], int t, const LdsLine &lds,
+                                         const float2 *__restrict__ tw) {
+  if constexpr (Plan<N>::S > 1) __syncthreads();
+  fft_stages<N, INV>(v, t, lds, tw);
+}
+
+}  // namespace sl

@@ -1,0 +1,500 @@
+// 2D transform passes on gfx950 (Algorithms 1 and 2 of the paper, computed
+// by the convolution theorem, Section 4).
+//
+// Data flow for a batch (filters psi_hat_i are real and even, so two real
+// subbands share one complex transform):
+//   forward   x --row DFT--> A --column DFT--> F            (once per image)
+//             F * (psi_a + i psi_b) --column IDFT--> T        (per pair)
+//             T --row IDFT--> c_a = Re, c_b = Im              (per pair)
+//   inverse   c_a + i c_b --row DFT--> U                      (per pair)
+//             ACC += (psi_a - i psi_b) * colDFT(U)            (sum over pairs)
+//             ACC / Psi_hat --column IDFT--> --row IDFT--> Re  (once per image)
+// Re of the last step equals the dual-frame reconstruction because the
+// imaginary cross terms psi_a C_b - psi_b C_a have Hermitian spectra and
+// therefore transform to purely imaginary signals.
+//
+// Each block owns M lines of one image; the FFT of a line runs in registers
+// with LDS exchanges between radix stages (fft_core.hpp).  Row passes read
+// and write whole rows; column passes move M adjacent columns per row.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "dispatch.hpp"
+#include "fft_core.hpp"
+
+namespace sl {
+
+template <int N>
+struct Tile {
+  static constexpr int NT = Plan<N>::NT;
+  static constexpr int E = Plan<N>::E;
+  static constexpr int M = NT >= 128 ? 8 : 16;     // lines per block
+  static constexpr int THREADS = M * NT;
+};
+
+// ---------------------------------------------------------------------------
+// storage encode / decode
+// ---------------------------------------------------------------------------
+template <int DT>
+struct Store;
+template <>
+struct Store<0> {
+  using T = float;
+  __device__ static T enc(float v) { return v; }
+  __device__ static float dec(T v) { return v; }
+};
+template <>
+struct Store<1> {
+  using T = __half;
+  __device__ static T enc(float v) { return __float2half_rn(v); }
+  __device__ static float dec(T v) { return __half2float(v); }
+};
+template <>
+struct Store<2> {
+  using T = __hip_bfloat16;
+  __device__ static T enc(float v) { return __float2bfloat16(v); }
+  __device__ static float dec(T v) { return __bfloat162float(v); }
+};
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// forward
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(Tile<N>::THREADS)
+k_rows_real_fft(const float *__restrict__ x, float2 *__restrict__ A, unsigned *__restrict__ xmax,
+                int H, const float2 *__restrict__ tw) {
+  constexpr int NT = Tile<N>::NT, M = Tile<N>::M, E = Tile<N>::E;
+  __shared__ float2 lds[M * N];
+  const int t = threadIdx.x % NT, m = threadIdx.x / NT;
+  const int row = blockIdx.x * M + m, b = blockIdx.y;
+  const bool ok = row < H;
+  const size_t off = ((size_t)b * H + (ok ? row : 0)) * N;
+  float2 v[E];
+  float amax = 0.f;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    float a = ok ? x[off + t + e * NT] : 0.f;
+    v[e] = make_float2(a, 0.f);
+    amax = fmaxf(amax, fabsf(a));
+  }
+  if (xmax) {
+    if (Tile<N>::THREADS % 64 == 0) {
+      amax = wave_max(amax);
+      if ((threadIdx.x & 63) == 0) atomicMax(xmax + b, __float_as_uint(amax));
+    } else {
+      atomicMax(xmax + b, __float_as_uint(amax));   // partial wave: no cross-lane reduction
+    }
+  }
+  fft_line<N, false>(v, t, LdsLine{lds + m * N, 1}, tw);
+  if (ok) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) A[off + t + e * NT] = v[e];
+  }
+}
+
+template <int N>
+__global__ void __launch_bounds__(Tile<N>::THREADS)
+k_cols_fft(const float2 *__restrict__ A, float2 *__restrict__ F, int W,
+           const float2 *__restrict__ tw) {
+  constexpr int NT = Tile<N>::NT, M = Tile<N>::M, E = Tile<N>::E;
+  __shared__ float2 lds[M * N];
+  const int m = threadIdx.x % M, t = threadIdx.x / M;
+  const int col = blockIdx.x * M + m;
+  const bool ok = col < W;
+  const size_t base = (size_t)blockIdx.y * N * W + (ok ? col : 0);
+  float2 v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = ok ? A[base + (size_t)(t + e * NT) * W] : make_float2(0.f, 0.f);
+  fft_line<N, false>(v, t, LdsLine{lds + m, M}, tw);
+  if (ok) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) F[base + (size_t)(t + e * NT) * W] = v[e];
+  }
+}
+
+template <int N>
+__global__ void __launch_bounds__(Tile<N>::THREADS)
+k_cols_filter_ifft(const float2 *__restrict__ F, const float *__restrict__ filt,
+                   float2 *__restrict__ T, int W, int R, int b0, int p0, int np,
+                   const float2 *__restrict__ tw) {
+  constexpr int NT = Tile<N>::NT, M = Tile<N>::M, E = Tile<N>::E;
+  __shared__ float2 lds[M * N];
+  const int m = threadIdx.x % M, t = threadIdx.x / M;
+  const int col = blockIdx.x * M + m;
+  const bool ok = col < W;
+  const int cc = ok ? col : 0;
+  const int b = b0 + blockIdx.y;
+  const size_t plane = (size_t)N * W;
+  float2 f[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) f[e] = F[(size_t)b * plane + (size_t)(t + e * NT) * W + cc];
+  for (int pp = 0; pp < np; ++pp) {
+    const int ia = 2 * (p0 + pp), ib = ia + 1;
+    const float *fa = filt + (size_t)ia * plane + cc;
+    const float *fb = filt + (size_t)(ib < R ? ib : ia) * plane + cc;
+    float2 v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const size_t o = (size_t)(t + e * NT) * W;
+      const float a = fa[o];
+      const float bb = ib < R ? fb[o] : 0.f;
+      v[e] = make_float2(f[e].x * a - f[e].y * bb, f[e].y * a + f[e].x * bb);
+    }
+    fft_line<N, true>(v, t, LdsLine{lds + m, M}, tw);
+    if (ok) {
+      float2 *To = T + ((size_t)blockIdx.y * np + pp) * plane + col;
+#pragma unroll
+      for (int e = 0; e < E; ++e) To[(size_t)(t + e * NT) * W] = v[e];
+    }
+  }
+}
+
+template <int N, int DT>
+__global__ void __launch_bounds__(Tile<N>::THREADS)
+k_rows_coef(const float2 *__restrict__ T, typename Store<DT>::T *__restrict__ coef,
+            const float *__restrict__ scales, int H, int R, int b0, int p0, int np, float inv_hw,
+            const float2 *__restrict__ tw) {
+  constexpr int NT = Tile<N>::NT, M = Tile<N>::M, E = Tile<N>::E;
+  __shared__ float2 lds[M * N];
+  const int t = threadIdx.x % NT, m = threadIdx.x / NT;
+  const int row = blockIdx.x * M + m;
+  const bool ok = row < H;
+  const int rr = ok ? row : 0;
+  const int pp = blockIdx.y, bl = blockIdx.z, b = b0 + bl;
+  const int ia = 2 * (p0 + pp), ib = ia + 1;
+  const size_t plane = (size_t)H * N;
+  const float2 *Ti = T + ((size_t)bl * np + pp) * plane + (size_t)rr * N;
+  float2 v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = Ti[t + e * NT];
+  fft_line<N, true>(v, t, LdsLine{lds + m * N, 1}, tw);
+  if (!ok) return;
+  float sa = inv_hw, sb = inv_hw;
+  if (DT != 0) {
+    sa = inv_hw / scales[(size_t)b * R + ia];
+    if (ib < R) sb = inv_hw / scales[(size_t)b * R + ib];
+  }
+  auto *ca = coef + ((size_t)b * R + ia) * plane + (size_t)row * N;
+#pragma unroll
+  for (int e = 0; e < E; ++e) ca[t + e * NT] = Store<DT>::enc(v[e].x * sa);
+  if (ib < R) {
+    auto *cb = coef + ((size_t)b * R + ib) * plane + (size_t)row * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) cb[t + e * NT] = Store<DT>::enc(v[e].y * sb);
+  }
+}
+
+// scale_{b,i} = 2^(ceil(log2(max|x_b| * ||psi_i||_1)) - 15): |c| <= max|x| ||psi||_1
+// (Young), so the stored values stay below 2^15 in magnitude.
+__global__ void k_scales(const unsigned *__restrict__ xmax, const float *__restrict__ l1,
+                         float *__restrict__ scales, int B, int R) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B * R) return;
+  float bound = __uint_as_float(xmax[i / R]) * l1[i % R];
+  scales[i] = bound > 0.f ? exp2f(ceilf(log2f(bound)) - 15.f) : 1.f;
+}
+
+__global__ void k_zero_u32(unsigned *p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// inverse
+// ---------------------------------------------------------------------------
+template <int N, int DT>
+__global__ void __launch_bounds__(Tile<N>::THREADS)
+k_rows_coef_fft(const typename Store<DT>::T *__restrict__ coef, const float *__restrict__ scales,
+                float2 *__restrict__ U, int H, int R, int b0, int p0, int np, ThrArgs thr,
+                const float2 *__restrict__ tw) {
+  constexpr int NT = Tile<N>::NT, M = Tile<N>::M, E = Tile<N>::E;
+  __shared__ float2 lds[M * N];
+  const int t = threadIdx.x % NT, m = threadIdx.x / NT;
+  const int row = blockIdx.x * M + m;
+  const bool ok = row < H;
+  const int rr = ok ? row : 0;
+  const int pp = blockIdx.y, bl = blockIdx.z, b = b0 + bl;
+  const int ia = 2 * (p0 + pp), ib = ia + 1;
+  const bool has_b = ib < R;
+  const size_t plane = (size_t)H * N;
+  float sa = 1.f, sb = 1.f;
+  if (DT != 0) {
+    sa = scales[(size_t)b * R + ia];
+    if (has_b) sb = scales[(size_t)b * R + ib];
+  }
+  float da = 0.f, db = 0.f;
+  if (thr.sigma) {
+    const float sg = thr.sigma[b];
+    const int ja = thr.jof[ia];
+    if (ja >= 0) da = (thr.K[ja] * sg) * thr.l2[ia];
+    if (has_b) {
+      const int jb = thr.jof[ib];
+      if (jb >= 0) db = (thr.K[jb] * sg) * thr.l2[ib];
+    }
+  }
+  const auto *ca = coef + ((size_t)b * R + ia) * plane + (size_t)rr * N;
+  const auto *cb = coef + ((size_t)b * R + (has_b ? ib : ia)) * plane + (size_t)rr * N;
+  float2 v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    float a = Store<DT>::dec(ca[t + e * NT]) * sa;
+    float bb = has_b ? Store<DT>::dec(cb[t + e * NT]) * sb : 0.f;
+    if (!(fabsf(a) >= da)) a = 0.f;
+    if (!(fabsf(bb) >= db)) bb = 0.f;
+    v[e] = make_float2(a, bb);
+  }
+  fft_line<N, false>(v, t, LdsLine{lds + m * N, 1}, tw);
+  if (ok) {
+    float2 *Uo = U + ((size_t)bl * np + pp) * plane + (size_t)row * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) Uo[t + e * NT] = v[e];
+  }
+}
+
+template <int N>
+__global__ void __launch_bounds__(Tile<N>::THREADS)
+k_cols_fft_acc(const float2 *__restrict__ U, const float *__restrict__ filt,
+               const float *__restrict__ psi, float2 *__restrict__ ACC, int W, int R, int b0,
+               int p0, int np, int first, int last, const float2 *__restrict__ tw) {
+  constexpr int NT = Tile<N>::NT, M = Tile<N>::M, E = Tile<N>::E;
+  __shared__ float2 lds[M * N];
+  const int m = threadIdx.x % M, t = threadIdx.x / M;
+  const int col = blockIdx.x * M + m;
+  const bool ok = col < W;
+  const int cc = ok ? col : 0;
+  const int b = b0 + blockIdx.y;
+  const size_t plane = (size_t)N * W;
+  float2 *accp = ACC + (size_t)b * plane + cc;
+  float2 acc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+    acc[e] = first ? make_float2(0.f, 0.f) : accp[(size_t)(t + e * NT) * W];
+  for (int pp = 0; pp < np; ++pp) {
+    const int ia = 2 * (p0 + pp), ib = ia + 1;
+    const float2 *Ui = U + ((size_t)blockIdx.y * np + pp) * plane + cc;
+    float2 v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = Ui[(size_t)(t + e * NT) * W];
+    fft_line<N, false>(v, t, LdsLine{lds + m, M}, tw);
+    const float *fa = filt + (size_t)ia * plane + cc;
+    const float *fb = filt + (size_t)(ib < R ? ib : ia) * plane + cc;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const size_t o = (size_t)(t + e * NT) * W;
+      const float a = fa[o];
+      const float bb = ib < R ? fb[o] : 0.f;
+      // (psi_a - i psi_b) * v
+      acc[e].x += a * v[e].x + bb * v[e].y;
+      acc[e].y += a * v[e].y - bb * v[e].x;
+    }
+  }
+  if (last) {
+    const float *ps = psi + cc;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const float d = ps[(size_t)(t + e * NT) * W];
+      acc[e] = make_float2(acc[e].x / d, acc[e].y / d);
+    }
+    fft_line<N, true>(acc, t, LdsLine{lds + m, M}, tw);
+  }
+  if (ok) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) accp[(size_t)(t + e * NT) * W] = acc[e];
+  }
+}
+
+template <int N>
+__global__ void __launch_bounds__(Tile<N>::THREADS)
+k_rows_real_ifft(const float2 *__restrict__ V, float *__restrict__ x, int H, float inv_hw,
+                 const float2 *__restrict__ tw) {
+  constexpr int NT = Tile<N>::NT, M = Tile<N>::M, E = Tile<N>::E;
+  __shared__ float2 lds[M * N];
+  const int t = threadIdx.x % NT, m = threadIdx.x / NT;
+  const int row = blockIdx.x * M + m, b = blockIdx.y;
+  const bool ok = row < H;
+  const size_t off = ((size_t)b * H + (ok ? row : 0)) * N;
+  float2 v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = V[off + t + e * NT];
+  fft_line<N, true>(v, t, LdsLine{lds + m * N, 1}, tw);
+  if (ok) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) x[off + t + e * NT] = v[e].x * inv_hw;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers: runtime length -> template instance
+// ---------------------------------------------------------------------------
+#define SL_FOR_EACH_N(X) \
+  X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
+
+bool lines_supported(int n) {
+  switch (n) {
+#define X(N) case N:
+    SL_FOR_EACH_N(X)
+#undef X
+    return true;
+    default:
+      return false;
+  }
+}
+
+template <int N>
+static dim3 row_grid(int H, int y, int z = 1) {
+  return dim3((H + Tile<N>::M - 1) / Tile<N>::M, y, z);
+}
+
+hipError_t launch_rows_real_fft(const Sys2D &s, const float *x, float2 *A, unsigned *xmax, int B,
+                                hipStream_t st) {
+  switch (s.W) {
+#define X(N)                                                                                  \
+  case N:                                                                                     \
+    hipLaunchKernelGGL(k_rows_real_fft<N>, row_grid<N>(s.H, B), dim3(Tile<N>::THREADS), 0, st, \
+                       x, A, xmax, s.H, s.twW);                                               \
+    break;
+    SL_FOR_EACH_N(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cols_fft(const Sys2D &s, const float2 *A, float2 *F, int B, hipStream_t st) {
+  switch (s.H) {
+#define X(N)                                                                                    \
+  case N:                                                                                       \
+    hipLaunchKernelGGL(k_cols_fft<N>, row_grid<N>(s.W, B), dim3(Tile<N>::THREADS), 0, st, A, F, \
+                       s.W, s.twH);                                                             \
+    break;
+    SL_FOR_EACH_N(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cols_filter_ifft(const Sys2D &s, const float2 *F, float2 *T, Chunk c,
+                                   hipStream_t st) {
+  switch (s.H) {
+#define X(N)                                                                                 \
+  case N:                                                                                    \
+    hipLaunchKernelGGL(k_cols_filter_ifft<N>, row_grid<N>(s.W, c.nb), dim3(Tile<N>::THREADS), \
+                       0, st, F, s.filt, T, s.W, s.R, c.b0, c.p0, c.np, s.twH);              \
+    break;
+    SL_FOR_EACH_N(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int DT>
+static hipError_t rows_coef_dt(const Sys2D &s, const float2 *T, void *coef, const float *scales,
+                               Chunk c, hipStream_t st) {
+  using CT = typename Store<DT>::T;
+  const float inv_hw = 1.0f / ((float)s.H * (float)s.W);
+  switch (s.W) {
+#define X(N)                                                                                     \
+  case N:                                                                                        \
+    hipLaunchKernelGGL((k_rows_coef<N, DT>), row_grid<N>(s.H, c.np, c.nb),                       \
+                       dim3(Tile<N>::THREADS), 0, st, T, (CT *)coef, scales, s.H, s.R, c.b0, c.p0, \
+                       c.np, inv_hw, s.twW);                                                     \
+    break;
+    SL_FOR_EACH_N(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_coef(const Sys2D &s, const float2 *T, void *coef, const float *scales,
+                            Chunk c, hipStream_t st) {
+  if (s.dtype == 1) return rows_coef_dt<1>(s, T, coef, scales, c, st);
+  if (s.dtype == 2) return rows_coef_dt<2>(s, T, coef, scales, c, st);
+  return rows_coef_dt<0>(s, T, coef, scales, c, st);
+}
+
+hipError_t launch_scales(const Sys2D &s, const unsigned *xmax, float *scales, int B,
+                         hipStream_t st) {
+  int n = B * s.R;
+  hipLaunchKernelGGL(k_scales, dim3((n + 255) / 256), dim3(256), 0, st, xmax, s.l1, scales, B, s.R);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(unsigned *p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_u32, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+template <int DT>
+static hipError_t rows_coef_fft_dt(const Sys2D &s, const void *coef, const float *scales,
+                                   float2 *U, Chunk c, const ThrArgs &thr, hipStream_t st) {
+  using CT = typename Store<DT>::T;
+  switch (s.W) {
+#define X(N)                                                                                   \
+  case N:                                                                                      \
+    hipLaunchKernelGGL((k_rows_coef_fft<N, DT>), row_grid<N>(s.H, c.np, c.nb),                 \
+                       dim3(Tile<N>::THREADS), 0, st, (const CT *)coef, scales, U, s.H, s.R,   \
+                       c.b0, c.p0, c.np, thr, s.twW);                                          \
+    break;
+    SL_FOR_EACH_N(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_coef_fft(const Sys2D &s, const void *coef, const float *scales, float2 *U,
+                                Chunk c, const ThrArgs &thr, hipStream_t st) {
+  if (s.dtype == 1) return rows_coef_fft_dt<1>(s, coef, scales, U, c, thr, st);
+  if (s.dtype == 2) return rows_coef_fft_dt<2>(s, coef, scales, U, c, thr, st);
+  return rows_coef_fft_dt<0>(s, coef, scales, U, c, thr, st);
+}
+
+hipError_t launch_cols_fft_acc(const Sys2D &s, const float2 *U, float2 *ACC, Chunk c, bool first,
+                               bool last, hipStream_t st) {
+  switch (s.H) {
+#define X(N)                                                                                    \
+  case N:                                                                                       \
+    hipLaunchKernelGGL(k_cols_fft_acc<N>, row_grid<N>(s.W, c.nb), dim3(Tile<N>::THREADS), 0, st, \
+                       U, s.filt, s.psi, ACC, s.W, s.R, c.b0, c.p0, c.np, (int)first,           \
+                       (int)last, s.twH);                                                       \
+    break;
+    SL_FOR_EACH_N(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_real_ifft(const Sys2D &s, const float2 *V, float *x, int B, hipStream_t st) {
+  const float inv_hw = 1.0f / ((float)s.H * (float)s.W);
+  switch (s.W) {
+#define X(N)                                                                                 \
+  case N:                                                                                    \
+    hipLaunchKernelGGL(k_rows_real_ifft<N>, row_grid<N>(s.H, B), dim3(Tile<N>::THREADS), 0, \
+                       st, V, x, s.H, inv_hw, s.twW);                                        \
+    break;
+    SL_FOR_EACH_N(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace sl
