@@ -1,0 +1,202 @@
+#!/usr/bin/env python
+"""Throughput benchmark of the 2D digital shearlet transform on one MI355X.
+
+Workload (one step): 32 synthetic cartoon images of 512x512 with Gaussian
+noise sigma in {20, 30, 40}/255, shearlet system with 4 scales and shear
+levels [1, 1, 2, 2] (R = 49 subbands), forward transform, hard thresholding
+at K_j sigma ||psi_i||_2 with K = [3, 3, 3, 4] fused into the inverse, and
+the inverse transform.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line with coefficients/s (B R H W per step / step time), the
+roofline of the dominant pass measured with HIP events inside the timed
+region, and the FP64 CPU oracle timed on a bounded sample on this host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+WORKLOAD = dict(B=32, H=512, W=512, J=4, levels=[1, 1, 2, 2], K=[3.0, 3.0, 3.0, 4.0])
+
+
+def pass_work(name, launches_chunks, H, W, R, B):
+    """Algorithmic (bytes, flops) summed over the launches of one pass.
+
+    Bytes count what the method must move: the input read once, each
+    coefficient written once and read once, the output written once and the
+    filter tables read once per call (FFT intermediates excluded).  Flops
+    count 5 N log2 N per complex length-N line transform plus the pointwise
+    filter products."""
+    import math
+    hw = H * W
+    P = (R + 1) // 2
+    lgH, lgW = math.log2(H), math.log2(W)
+    by = fl = 0.0
+    if name == "rows_real_fft":
+        by = B * hw * 4
+        fl = B * H * 5 * W * lgW
+    elif name == "cols_fft":
+        fl = B * W * 5 * H * lgH
+    elif name == "cols_filter_ifft":
+        by = 2 * P * hw * 4
+        fl = B * P * (W * 5 * H * lgH + 6 * hw)
+    elif name == "rows_coef":
+        by = B * R * hw * 4
+        fl = B * P * H * 5 * W * lgW
+    elif name == "rows_coef_fft":
+        by = B * R * hw * 4
+        fl = B * P * H * 5 * W * lgW
+    elif name == "cols_fft_acc":
+        by = 2 * P * hw * 4 + hw * 4
+        fl = B * P * (W * 5 * H * lgH + 8 * hw) + B * W * 5 * H * lgH
+    elif name == "rows_real_ifft":
+        by = B * hw * 4
+        fl = B * H * 5 * W * lgW
+    return by, fl
+
+
+def cpu_baseline(seconds, sigmas, K, H, W, J, levels):
+    """FP64 oracle (numpy FFT, one thread) on a bounded sample of images."""
+    import numpy as np
+    from oracle import system as S
+    from oracle import transform as T
+    from paper_1402_5670_amd import synthetic as syn
+    sysm = S.build_2d((H, W), J, levels)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        clean, x = syn.noisy_cartoon2d(H, W, 2000 + n, float(sigmas[n % len(sigmas)]))
+        ts = time.perf_counter()
+        T.denoise(x, sysm, float(sigmas[n % len(sigmas)]), K)
+        n += 1
+        if time.perf_counter() - t0 >= seconds or n >= 16:
+            break
+    el = time.perf_counter() - t0
+    coeffs = n * sysm.R * H * W
+    return dict(value=coeffs / el, unit="coefficients/s", cores=1, kind="oracle",
+                sample=f"{n} images {H}x{W}, R={sysm.R}, fwd + hard threshold + inv in FP64 "
+                       f"(numpy.fft, single thread), filter build excluded, {el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the transform of a batch runs on a single "
+              "MI355X; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from oracle import transform as T   # PSNR only
+    from paper_1402_5670_amd import binding as Bd
+    from paper_1402_5670_amd import synthetic as syn
+
+    Bn, H, W, J, levels, K = (WORKLOAD[k] for k in ("B", "H", "W", "J", "levels", "K"))
+    dev = torch.device("cuda:0")
+    sig = syn.batch_sigmas(Bn)
+    pairs = [syn.noisy_cartoon2d(H, W, 2000 + b, float(sig[b])) for b in range(Bn)]
+    x = torch.from_numpy(np.stack([p[1] for p in pairs]).astype(np.float32)).to(dev)
+    sigma = torch.from_numpy(sig.astype(np.float32)).to(dev)
+    sysg = Bd.System((H, W), J, levels)
+    R = sysg.R
+    coeffs, scales = sysg.alloc_coeffs(Bn, dev)
+    out = torch.empty_like(x)
+    ws = sysg.workspace(Bn, dev)
+
+    def step():
+        sysg.forward(x, coeffs, scales, workspace=ws)
+        sysg.inverse(coeffs, scales, sigma=sigma, K=K, out=out, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    Bd.timing_reset()
+    Bd.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    Bd.timing_enable(False)
+    rep = Bd.timing_report()
+    Bd.timing_reset()
+
+    ms_step = (t1 - t0) * 1000.0 / args.steps
+    coeff_per_step = Bn * R * H * W
+    value = coeff_per_step / (ms_step / 1000.0)
+
+    # roofline of the dominant pass
+    passes = {}
+    for name, (ms, n) in rep.items():
+        by, fl = pass_work(name, n, H, W, R, Bn)
+        per_step_ms = ms / args.steps
+        passes[name] = dict(ms_per_step=per_step_ms, launches_per_step=n / args.steps,
+                            avg_launch_us=1000.0 * ms / n,
+                            GBps=by / (per_step_ms * 1e6) if by else 0.0,
+                            TFLOPs=fl / (per_step_ms * 1e9))
+    dom = max(passes, key=lambda k: passes[k]["ms_per_step"])
+    d = passes[dom]
+    by, fl = pass_work(dom, 0, H, W, R, Bn)
+    hbm_frac = d["GBps"] / HBM_PEAK_GBS
+    alu_frac = d["TFLOPs"] / FP32_VECTOR_PEAK_TFLOPS
+    launches = d["launches_per_step"]
+    if hbm_frac >= alu_frac:
+        roof = {"bound": "hbm", "achieved": round(d["GBps"], 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(hbm_frac, 4)}
+    else:
+        roof = {"bound": "alu", "achieved": round(d["TFLOPs"], 2),
+                "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(alu_frac, 4)}
+    roof.update({"kernel": dom, "avg_launch_us": round(d["avg_launch_us"], 2),
+                 "launches_per_step": launches, "traffic": None})
+
+    step_bytes = sum(pass_work(n, 0, H, W, R, Bn)[0] for n in rep)
+    psnr_noisy = float(np.mean([T.psnr(pairs[b][0], pairs[b][1]) for b in range(Bn)]))
+    outn = out.cpu().numpy()
+    psnr_hard = float(np.mean([T.psnr(pairs[b][0], outn[b]) for b in range(Bn)]))
+
+    res = {
+        "metric": "coefficients/sec fwd+inv",
+        "value": value,
+        "unit": "coefficients/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"2D batched forward + hard threshold + inverse, {Bn} images "
+                               f"{H}x{W}, 4 scales, shearLevels {levels}, R={R}, K={K}",
+                   "global_batch": Bn, "coefficients_per_step": coeff_per_step},
+        "hbm_algorithmic_GBps_step": step_bytes / (ms_step * 1e6),
+        "hbm_frac_step": step_bytes / (ms_step * 1e6) / HBM_PEAK_GBS,
+        "psnr_noisy_db": psnr_noisy,
+        "psnr_hard_db": psnr_hard,
+        "passes": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in passes.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(args.cpu_seconds, sig, K, H, W, J, levels)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

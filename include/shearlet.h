@@ -137,6 +137,18 @@ int sl_denoise(const sl_system *s, const float *x_dev, int batch, const float *s
                const float *K_host, void *coeffs_dev, float *scales_dev, float *out_dev,
                void *workspace_dev, size_t workspace_bytes, void *stream);
 
+/* ---- diagnostics: per-pass device timing ---------------------------------
+ * When enabled, every kernel launch of the transforms is bracketed by a pair
+ * of HIP events recorded on the launch stream; sl_timing_query synchronises
+ * those events and returns the summed elapsed time and the launch count of
+ * one pass.  Passes are numbered 0..sl_timing_num_passes()-1 and named by
+ * sl_timing_pass_name.  Process-wide state; not thread-safe.                */
+int sl_timing_enable(int on);
+int sl_timing_reset(void);
+int sl_timing_num_passes(void);
+const char *sl_timing_pass_name(int pass);
+int sl_timing_query(int pass, double *total_ms_out, int *launches_out);
+
 #ifdef __cplusplus
 }
 #endif

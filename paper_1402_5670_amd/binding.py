@@ -69,6 +69,12 @@ _SIGS = {
     "sl_denoise": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                     ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+    "sl_timing_enable": ([ctypes.c_int], ctypes.c_int),
+    "sl_timing_reset": ([], ctypes.c_int),
+    "sl_timing_num_passes": ([], ctypes.c_int),
+    "sl_timing_pass_name": ([ctypes.c_int], ctypes.c_char_p),
+    "sl_timing_query": ([ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                         ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
 }
 
 
@@ -89,6 +95,25 @@ def lib():
 
 def exported_symbols():
     return list(_SIGS)
+
+
+def timing_enable(on=True):
+    check(lib().sl_timing_enable(int(bool(on))))
+
+
+def timing_reset():
+    check(lib().sl_timing_reset())
+
+
+def timing_report():
+    """{pass name: (total ms, launches)} for the launches since the last reset."""
+    out = {}
+    for p in range(lib().sl_timing_num_passes()):
+        ms, n = ctypes.c_double(), ctypes.c_int()
+        check(lib().sl_timing_query(p, ctypes.byref(ms), ctypes.byref(n)))
+        if n.value:
+            out[lib().sl_timing_pass_name(p).decode()] = (ms.value, n.value)
+    return out
 
 
 def check(rc):

@@ -43,6 +43,8 @@ struct sl_system {
   float *d_psi = nullptr;     // Psi_hat on the grid
   float *d_l2 = nullptr, *d_l1 = nullptr;
   int *d_jof = nullptr;
+  sl::Sub3D *d_subs3 = nullptr;   // 3D: per-subband factor descriptors
+  float *d_tab3 = nullptr;        // 3D: factor tables
   std::map<int, float2 *> d_tw;
   std::vector<void *> allocs;
 };
@@ -89,6 +91,12 @@ void chunk_plan(const sl_system *s, int B, int &nb, int &np) {
     nb = (int)std::max<size_t>(1, cap / plane);
     np = 1;
   }
+  // grid limits: chunk images * pairs (times the depth in 3D) index grid.y
+  const int depth = s->cfg.ndim == 3 ? (int)s->cfg.dims[0] : 1;
+  while ((int64_t)nb * np * depth > 65535) {
+    if (np > 1) np = (np + 1) / 2;
+    else nb = (nb + 1) / 2;
+  }
 }
 
 struct Layout {
@@ -107,26 +115,47 @@ Layout layout(const sl_system *s, int B) {
   return L;
 }
 
-sl::Sys2D view2d(const sl_system *s) {
+// A 2D view of the system for the line kernels: H lines of length W.  In 3D
+// the row view is (D*H) x W, the y view H x W per z-slice and the z view
+// D x (H*W) per volume.
+sl::Sys2D view2d(const sl_system *s, int H, int W, int nH, int nW) {
   sl::Sys2D v;
-  v.H = (int)s->cfg.dims[0];
-  v.W = (int)s->cfg.dims[1];
+  v.H = H;
+  v.W = W;
   v.R = s->R;
   v.dtype = s->cfg.dtype;
   v.filt = s->d_filt;
   v.psi = s->d_psi;
   v.l1 = s->d_l1;
-  v.twH = s->d_tw.at(v.H);
-  v.twW = s->d_tw.at(v.W);
+  v.twH = nH ? s->d_tw.at(nH) : nullptr;
+  v.twW = nW ? s->d_tw.at(nW) : nullptr;
+  return v;
+}
+
+sl::Sys2D view2d(const sl_system *s) {
+  int H = (int)s->cfg.dims[0], W = (int)s->cfg.dims[1];
+  return view2d(s, H, W, H, W);
+}
+
+sl::Sys3D view3d(const sl_system *s) {
+  sl::Sys3D v;
+  v.D = (int)s->cfg.dims[0];
+  v.H = (int)s->cfg.dims[1];
+  v.W = (int)s->cfg.dims[2];
+  v.R = s->R;
+  v.dtype = s->cfg.dtype;
+  v.subs = s->d_subs3;
+  v.tab = s->d_tab3;
+  v.psi = s->d_psi;
+  v.twD = s->d_tw.at(v.D);
   return v;
 }
 
 int check_call(const sl_system *s, int batch, const void *a, const void *b, void *ws,
                size_t ws_bytes) {
   if (!s) return fail(SL_EINVAL, "system is NULL");
-  if (batch < 1) return fail(SL_EINVAL, "batch must be >= 1");
+  if (batch < 1 || batch > 65535) return fail(SL_EINVAL, "batch must be in 1..65535");
   if (!a || !b || !ws) return fail(SL_EINVAL, "NULL buffer");
-  if (s->cfg.ndim != 2) return fail(SL_EUNSUPPORTED, "3D transforms are not available");
   size_t need = layout(s, batch).total;
   if (ws_bytes < need)
     return fail(SL_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
@@ -141,6 +170,107 @@ int check_call(const sl_system *s, int batch, const void *a, const void *b, void
     hipError_t e_ = (expr);                            \
     if (e_ != hipSuccess) return hip_fail(e_, #expr);  \
   } while (0)
+
+// ---- per-pass event timing ----------------------------------------------
+enum Pass {
+  P_ROWS_REAL_FFT = 0,
+  P_COLS_FFT,
+  P_COLS_FILTER_IFFT,
+  P_ROWS_COEF,
+  P_ROWS_COEF_FFT,
+  P_COLS_FFT_ACC,
+  P_ROWS_REAL_IFFT,
+  P_AUX,
+  P_COUNT
+};
+const char *kPassNames[P_COUNT] = {"rows_real_fft",   "cols_fft",      "cols_filter_ifft",
+                                   "rows_coef",       "rows_coef_fft", "cols_fft_acc",
+                                   "rows_real_ifft",  "aux"};
+
+struct Timing {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[P_COUNT];
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  void recycle() {
+    for (auto &v : ev)
+      for (auto &p : v) {
+        pool.push_back(p.first);
+        pool.push_back(p.second);
+      }
+    for (auto &v : ev) v.clear();
+  }
+} g_timing;
+
+template <class F>
+hipError_t timed(int pass, hipStream_t st, F &&launch) {
+  if (!g_timing.on) return launch();
+  hipEvent_t a = g_timing.get(), b = g_timing.get();
+  (void)hipEventRecord(a, st);
+  hipError_t e = launch();
+  (void)hipEventRecord(b, st);
+  g_timing.ev[pass].push_back({a, b});
+  return e;
+}
+
+#define SL_LAUNCH(pass, st, expr) SL_TRY(timed(pass, st, [&]() { return (expr); }))
+
+int forward3d(const sl_system *s, const float *x, int batch, void *coef, float *scales,
+              float2 *F, float2 *T, unsigned *xmax, hipStream_t st) {
+  const int D = (int)s->cfg.dims[0], H = (int)s->cfg.dims[1], W = (int)s->cfg.dims[2];
+  const bool scaled = s->cfg.dtype != SL_F32;
+  const sl::Sys2D vr = view2d(s, D * H, W, 0, W);       // x lines
+  const sl::Sys2D vy = view2d(s, H, W, H, 0);           // y lines per z-slice
+  const sl::Sys2D vz = view2d(s, D, H * W, D, 0);       // z lines per volume
+  const sl::Sys3D v3 = view3d(s);
+  if (scaled) SL_LAUNCH(P_AUX, st, sl::launch_zero_u32(xmax, batch, st));
+  SL_LAUNCH(P_ROWS_REAL_FFT, st, sl::launch_rows_real_fft(vr, x, F, scaled ? xmax : nullptr, batch, st));
+  SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, F, F, batch * D, false, st));
+  SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vz, F, F, batch, false, st));
+  if (scaled) SL_LAUNCH(P_AUX, st, sl::launch_scales(vr, xmax, scales, batch, st));
+  int nb, np;
+  chunk_plan(s, batch, nb, np);
+  const int P = (s->R + 1) / 2;
+  for (int b0 = 0; b0 < batch; b0 += nb)
+    for (int p0 = 0; p0 < P; p0 += np) {
+      sl::Chunk c{b0, std::min(nb, batch - b0), p0, std::min(np, P - p0)};
+      SL_LAUNCH(P_COLS_FILTER_IFFT, st, sl::launch_z_filter_ifft(v3, F, T, c, st));
+      SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, T, T, c.nb * c.np * D, true, st));
+      SL_LAUNCH(P_ROWS_COEF, st, sl::launch_rows_coef(vr, T, coef, scales, c, st));
+    }
+  return SL_OK;
+}
+
+int inverse3d(const sl_system *s, const void *coef, const float *scales, int batch,
+              const sl::ThrArgs &thr, float *x, float2 *ACC, float2 *U, hipStream_t st) {
+  const int D = (int)s->cfg.dims[0], H = (int)s->cfg.dims[1], W = (int)s->cfg.dims[2];
+  const sl::Sys2D vr = view2d(s, D * H, W, 0, W);
+  const sl::Sys2D vy = view2d(s, H, W, H, 0);
+  const sl::Sys3D v3 = view3d(s);
+  int nb, np;
+  chunk_plan(s, batch, nb, np);
+  const int P = (s->R + 1) / 2;
+  for (int b0 = 0; b0 < batch; b0 += nb)
+    for (int p0 = 0; p0 < P; p0 += np) {
+      sl::Chunk c{b0, std::min(nb, batch - b0), p0, std::min(np, P - p0)};
+      SL_LAUNCH(P_ROWS_COEF_FFT, st, sl::launch_rows_coef_fft(vr, coef, scales, U, c, thr, st));
+      SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, U, U, c.nb * c.np * D, false, st));
+      SL_LAUNCH(P_COLS_FFT_ACC, st,
+                sl::launch_z_fft_acc(v3, U, ACC, c, p0 == 0, p0 + c.np == P, st));
+    }
+  SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, ACC, ACC, batch * D, true, st));
+  SL_LAUNCH(P_ROWS_REAL_IFFT, st, sl::launch_rows_real_ifft(vr, ACC, x, batch, st));
+  return SL_OK;
+}
 
 }  // namespace
 
@@ -188,16 +318,13 @@ int sl_build_system(const sl_config *cfg, sl_system **out) {
     delete s;
     return fail(rc, err);
   }
-  if (s->cfg.ndim != 2) {
-    delete s;
-    return fail(SL_EUNSUPPORTED, "3D systems are not available");
-  }
   const int64_t npix = s->cfg.npix();
+  const bool is3d = s->cfg.ndim == 3;
   int R = 0;
   sl_config_num_subbands(cfg, &R);
-  std::vector<double> filt64((size_t)R * npix);
+  std::vector<double> filt64(is3d ? 0 : (size_t)R * npix);
   slh::Bank bank;
-  rc = slh::build_bank(s->cfg, bank, filt64.data(), err);
+  rc = slh::build_bank(s->cfg, bank, is3d ? nullptr : filt64.data(), err);
   if (rc != SL_OK) {
     delete s;
     return fail(rc, err);
@@ -224,11 +351,53 @@ int sl_build_system(const sl_config *cfg, sl_system **out) {
     l1f[i] = std::nextafter((float)bank.l1[i], INFINITY);
     jof[i] = bank.subbands[i].cone == 0 ? -1 : bank.subbands[i].j;
   }
-  if ((rc = dev_upload(s, f32, &s->d_filt)) || (rc = dev_upload(s, psi32, &s->d_psi)) ||
+  if ((!is3d && (rc = dev_upload(s, f32, &s->d_filt))) || (rc = dev_upload(s, psi32, &s->d_psi)) ||
       (rc = dev_upload(s, l2f, &s->d_l2)) || (rc = dev_upload(s, l1f, &s->d_l1)) ||
       (rc = dev_upload(s, jof, &s->d_jof))) {
     sl_free_system(s);
     return rc;
+  }
+  if (is3d) {
+    // factor tables: lowpass lines per axis, g lines per (scale, axis) and the
+    // Phi planes per (scale, shear, main axis, secondary axis)
+    slh::Tables3D t;
+    slh::build_tables_3d(s->cfg, t);
+    std::vector<float> tab;
+    auto push = [&](const std::vector<double> &v) {
+      int off = (int)tab.size();
+      for (double d : v) tab.push_back((float)d);
+      return off;
+    };
+    int low_off[4] = {0, 0, 0, 0};
+    for (int ax = 1; ax <= 3; ++ax) low_off[ax] = push(t.low[ax - 1]);
+    std::vector<int> g_off(t.g.size()), p_off(t.planes.size());
+    for (size_t q = 0; q < t.g.size(); ++q) g_off[q] = push(t.g[q]);
+    for (size_t q = 0; q < t.planes.size(); ++q) p_off[q] = push(t.planes[q]);
+    static const int axes[4][3] = {{1, 2, 3}, {1, 2, 3}, {2, 1, 3}, {3, 1, 2}};
+    std::vector<sl::Sub3D> subs3(R);
+    for (int i = 0; i < R; ++i) {
+      const auto &b = bank.subbands[i];
+      sl::Sub3D d{};
+      d.cone = b.cone;
+      if (b.cone == 0) {
+        d.g_off = low_off[1];
+        d.p1_off = low_off[2];
+        d.p2_off = low_off[3];
+      } else {
+        d.am = axes[b.cone][0];
+        d.s1 = axes[b.cone][1];
+        d.s2 = axes[b.cone][2];
+        d.g_off = g_off[(size_t)b.j * 3 + d.am - 1];
+        d.p1_off = p_off[t.find(b.j, b.k1, d.am, d.s1)];
+        d.p2_off = p_off[t.find(b.j, b.k2, d.am, d.s2)];
+        d.n_main = s->cfg.n(d.am);
+      }
+      subs3[i] = d;
+    }
+    if ((rc = dev_upload(s, tab, &s->d_tab3)) || (rc = dev_upload(s, subs3, &s->d_subs3))) {
+      sl_free_system(s);
+      return rc;
+    }
   }
   for (int a = 0; a < s->cfg.ndim; ++a) {
     int N = (int)s->cfg.dims[a];
@@ -278,24 +447,25 @@ int sl_forward(const sl_system *s, const float *x_dev, int batch, void *coeffs_d
   const bool scaled = s->cfg.dtype != SL_F32;
   if (scaled && !scales_dev) return fail(SL_EINVAL, "scales_dev is required for F16/BF16 storage");
   hipStream_t st = (hipStream_t)stream;
-  const sl::Sys2D v = view2d(s);
   const Layout L = layout(s, batch);
   char *ws = (char *)workspace_dev;
   float2 *F = (float2 *)(ws + L.off_F);
   float2 *T = (float2 *)(ws + L.off_chunk);
   unsigned *xmax = (unsigned *)(ws + L.off_xmax);
-  if (scaled) SL_TRY(sl::launch_zero_u32(xmax, batch, st));
-  SL_TRY(sl::launch_rows_real_fft(v, x_dev, F, scaled ? xmax : nullptr, batch, st));
-  SL_TRY(sl::launch_cols_fft(v, F, F, batch, st));
-  if (scaled) SL_TRY(sl::launch_scales(v, xmax, scales_dev, batch, st));
+  if (s->cfg.ndim == 3) return forward3d(s, x_dev, batch, coeffs_dev, scales_dev, F, T, xmax, st);
+  const sl::Sys2D v = view2d(s);
+  if (scaled) SL_LAUNCH(P_AUX, st, sl::launch_zero_u32(xmax, batch, st));
+  SL_LAUNCH(P_ROWS_REAL_FFT, st, sl::launch_rows_real_fft(v, x_dev, F, scaled ? xmax : nullptr, batch, st));
+  SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(v, F, F, batch, false, st));
+  if (scaled) SL_LAUNCH(P_AUX, st, sl::launch_scales(v, xmax, scales_dev, batch, st));
   int nb, np;
   chunk_plan(s, batch, nb, np);
   const int P = (s->R + 1) / 2;
   for (int b0 = 0; b0 < batch; b0 += nb)
     for (int p0 = 0; p0 < P; p0 += np) {
       sl::Chunk c{b0, std::min(nb, batch - b0), p0, std::min(np, P - p0)};
-      SL_TRY(sl::launch_cols_filter_ifft(v, F, T, c, st));
-      SL_TRY(sl::launch_rows_coef(v, T, coeffs_dev, scales_dev, c, st));
+      SL_LAUNCH(P_COLS_FILTER_IFFT, st, sl::launch_cols_filter_ifft(v, F, T, c, st));
+      SL_LAUNCH(P_ROWS_COEF, st, sl::launch_rows_coef(v, T, coeffs_dev, scales_dev, c, st));
     }
   return SL_OK;
 }
@@ -317,21 +487,22 @@ int sl_inverse(const sl_system *s, const void *coeffs_dev, const float *scales_d
     for (int j = 0; j < s->cfg.J; ++j) thr.K[j] = K_host[j];
   }
   hipStream_t st = (hipStream_t)stream;
-  const sl::Sys2D v = view2d(s);
   const Layout L = layout(s, batch);
   char *ws = (char *)workspace_dev;
   float2 *ACC = (float2 *)(ws + L.off_F);
   float2 *U = (float2 *)(ws + L.off_chunk);
+  if (s->cfg.ndim == 3) return inverse3d(s, coeffs_dev, scales_dev, batch, thr, x_dev, ACC, U, st);
+  const sl::Sys2D v = view2d(s);
   int nb, np;
   chunk_plan(s, batch, nb, np);
   const int P = (s->R + 1) / 2;
   for (int b0 = 0; b0 < batch; b0 += nb)
     for (int p0 = 0; p0 < P; p0 += np) {
       sl::Chunk c{b0, std::min(nb, batch - b0), p0, std::min(np, P - p0)};
-      SL_TRY(sl::launch_rows_coef_fft(v, coeffs_dev, scales_dev, U, c, thr, st));
-      SL_TRY(sl::launch_cols_fft_acc(v, U, ACC, c, p0 == 0, p0 + c.np == P, st));
+      SL_LAUNCH(P_ROWS_COEF_FFT, st, sl::launch_rows_coef_fft(v, coeffs_dev, scales_dev, U, c, thr, st));
+      SL_LAUNCH(P_COLS_FFT_ACC, st, sl::launch_cols_fft_acc(v, U, ACC, c, p0 == 0, p0 + c.np == P, st));
     }
-  SL_TRY(sl::launch_rows_real_ifft(v, ACC, x_dev, batch, st));
+  SL_LAUNCH(P_ROWS_REAL_IFFT, st, sl::launch_rows_real_ifft(v, ACC, x_dev, batch, st));
   return SL_OK;
 }
 
@@ -344,6 +515,39 @@ int sl_denoise(const sl_system *s, const float *x_dev, int batch, const float *s
   if (rc) return rc;
   return sl_inverse(s, coeffs_dev, scales_dev, batch, sigma_dev, K_host, out_dev, workspace_dev,
                     workspace_bytes, stream);
+}
+
+int sl_timing_enable(int on) {
+  g_timing.on = on != 0;
+  return SL_OK;
+}
+
+int sl_timing_reset(void) {
+  g_timing.recycle();
+  return SL_OK;
+}
+
+int sl_timing_num_passes(void) { return P_COUNT; }
+
+const char *sl_timing_pass_name(int pass) {
+  return (pass >= 0 && pass < P_COUNT) ? kPassNames[pass] : nullptr;
+}
+
+int sl_timing_query(int pass, double *total_ms_out, int *launches_out) {
+  if (pass < 0 || pass >= P_COUNT || !total_ms_out || !launches_out)
+    return fail(SL_EINVAL, "bad timing query");
+  double tot = 0.0;
+  for (auto &p : g_timing.ev[pass]) {
+    hipError_t e = hipEventSynchronize(p.second);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, p.first, p.second);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    tot += ms;
+  }
+  *total_ms_out = tot;
+  *launches_out = (int)g_timing.ev[pass].size();
+  return SL_OK;
 }
 
 }  // extern "C"

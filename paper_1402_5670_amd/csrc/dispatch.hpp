@@ -38,8 +38,9 @@ bool lines_supported(int n);
 // x [B][H][W] real -> A [B][H][W] complex (row DFT); xmax[b] = max |x_b| bits
 hipError_t launch_rows_real_fft(const Sys2D &s, const float *x, float2 *A, unsigned *xmax, int B,
                                 hipStream_t st);
-// A -> F (column DFT)
-hipError_t launch_cols_fft(const Sys2D &s, const float2 *A, float2 *F, int B, hipStream_t st);
+// A -> F (column DFT, or inverse DFT without scaling when inverse is set)
+hipError_t launch_cols_fft(const Sys2D &s, const float2 *A, float2 *F, int B, bool inverse,
+                           hipStream_t st);
 // F, filters -> T[chunk] (filter pair multiply + column inverse DFT)
 hipError_t launch_cols_filter_ifft(const Sys2D &s, const float2 *F, float2 *T, Chunk c,
                                    hipStream_t st);
@@ -61,5 +62,28 @@ hipError_t launch_cols_fft_acc(const Sys2D &s, const float2 *U, float2 *ACC, Chu
                                bool last, hipStream_t st);
 // ACC -> x (row inverse DFT, real part, 1/(HW))
 hipError_t launch_rows_real_ifft(const Sys2D &s, const float2 *V, float *x, int B, hipStream_t st);
+
+// ---- 3D --------------------------------------------------------------------
+// Filter of one subband generated from its factors (see kernels3d.hip):
+//   lowpass (cone 0): tab[g_off + x] * tab[p1_off + y] * tab[p2_off + z]
+//   otherwise: g[xi_am] * plane1[xi_s1][xi_am] * plane2[xi_s2][xi_am] with
+//   axes numbered 1 = x (W), 2 = y (H), 3 = z (D) and planes of row length n_main.
+struct Sub3D {
+  int cone, am, s1, s2;
+  int g_off, p1_off, p2_off, n_main;
+};
+
+struct Sys3D {
+  int D, H, W, R, dtype;
+  const Sub3D *subs;          // [R]
+  const float *tab;           // factor tables
+  const float *psi;           // [D][H][W] Psi_hat
+  const float2 *twD;
+};
+
+hipError_t launch_z_filter_ifft(const Sys3D &s, const float2 *F, float2 *T, Chunk c,
+                                hipStream_t st);
+hipError_t launch_z_fft_acc(const Sys3D &s, const float2 *U, float2 *ACC, Chunk c, bool first,
+                            bool last, hipStream_t st);
 
 }  // namespace sl

@@ -99,7 +99,7 @@ k_rows_real_fft(const float *__restrict__ x, float2 *__restrict__ A, unsigned *_
   }
 }
 
-template <int N>
+template <int N, bool INV>
 __global__ void __launch_bounds__(Tile<N>::THREADS)
 k_cols_fft(const float2 *__restrict__ A, float2 *__restrict__ F, int W,
            const float2 *__restrict__ tw) {
@@ -112,7 +112,7 @@ k_cols_fft(const float2 *__restrict__ A, float2 *__restrict__ F, int W,
   float2 v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = ok ? A[base + (size_t)(t + e * NT) * W] : make_float2(0.f, 0.f);
-  fft_line<N, false>(v, t, LdsLine{lds + m, M}, tw);
+  fft_line<N, INV>(v, t, LdsLine{lds + m, M}, tw);
   if (ok) {
 #pragma unroll
     for (int e = 0; e < E; ++e) F[base + (size_t)(t + e * NT) * W] = v[e];
@@ -368,12 +368,17 @@ hipError_t launch_rows_real_fft(const Sys2D &s, const float *x, float2 *A, unsig
   return hipGetLastError();
 }
 
-hipError_t launch_cols_fft(const Sys2D &s, const float2 *A, float2 *F, int B, hipStream_t st) {
+hipError_t launch_cols_fft(const Sys2D &s, const float2 *A, float2 *F, int B, bool inverse,
+                           hipStream_t st) {
   switch (s.H) {
-#define X(N)                                                                                    \
-  case N:                                                                                       \
-    hipLaunchKernelGGL(k_cols_fft<N>, row_grid<N>(s.W, B), dim3(Tile<N>::THREADS), 0, st, A, F, \
-                       s.W, s.twH);                                                             \
+#define X(N)                                                                                  \
+  case N:                                                                                     \
+    if (inverse)                                                                              \
+      hipLaunchKernelGGL((k_cols_fft<N, true>), row_grid<N>(s.W, B), dim3(Tile<N>::THREADS), 0, \
+                         st, A, F, s.W, s.twH);                                               \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_cols_fft<N, false>), row_grid<N>(s.W, B), dim3(Tile<N>::THREADS), \
+                         0, st, A, F, s.W, s.twH);                                            \
     break;
     SL_FOR_EACH_N(X)
 #undef X
