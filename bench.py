@@ -77,7 +77,7 @@ def cpu_baseline(seconds, sigmas, K, H, W, J, levels):
         ts = time.perf_counter()
         T.denoise(x, sysm, float(sigmas[n % len(sigmas)]), K)
         n += 1
-        if time.perf_counter() - t0 >= seconds or n >= 16:
+        if time.perf_counter() - t0 >= seconds or n >= 64:
             break
     el = time.perf_counter() - t0
     coeffs = n * sysm.R * H * W
@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the transform of a batch runs on a single "
@@ -124,6 +126,12 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    if args.calib_copy_mib:
+        src = torch.empty(args.calib_copy_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     Bd.timing_reset()
     Bd.timing_enable(True)

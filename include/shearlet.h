@@ -137,6 +137,54 @@ int sl_denoise(const sl_system *s, const float *x_dev, int batch, const float *s
                const float *K_host, void *coeffs_dev, float *scales_dev, float *out_dev,
                void *workspace_dev, size_t workspace_bytes, void *stream);
 
+/* Adjoint of sl_inverse: c_i = IDFT(psi_hat_i / Psi_hat .* DFT(r)) for every
+ * subband, i.e. the forward transform with the dual filters of eq.
+ * dual_filter.  Used to back-propagate an image-domain loss through the
+ * reconstruction.  Requires SL_F32 storage.                                  */
+int sl_inverse_adjoint(const sl_system *s, const float *r_dev, int batch, float *coeffs_dev,
+                       void *workspace_dev, size_t workspace_bytes, void *stream);
+
+/* ---- learned shrinkage (an extension beyond the paper) -------------------
+ * A per-scale CNN maps each detail coefficient plane c (with the noise level
+ * sigma of its image) to gains g in [0, 1]:
+ *   x0 = (|c| / (sigma ||psi_i||_2), sigma * 255 / 50),
+ *   g  = sigmoid(conv3(relu(conv2(relu(conv1(x0)))))),  3x3 convolutions
+ *   with zero padding, 2 -> 32 -> 32 -> 1 channels; output g * c.
+ * Parameters: params_dev [J][SL_CNN_PARAMS] float32, one blob per scale:
+ *   W1[32][2][9] b1[32] W2[32][32][9] b2[32] W3[1][32][9] b3[1], weights
+ *   indexed [out][in][3 dy + dx].  The matrix-core kernels read bfloat16
+ *   operand copies built by sl_cnn_pack (call it after every update); they
+ *   accumulate in float32.  Coefficients must be SL_F32; 2D systems only.    */
+#define SL_CNN_PARAMS 10145
+size_t sl_cnn_packed_bytes(int J);
+int sl_cnn_pack(const float *params_dev, int J, void *packed_dev, void *stream);
+/* Workspace bytes of sl_cnn_apply (training = 0) or sl_cnn_backward (1).     */
+int sl_cnn_workspace_size(const sl_system *s, int batch, int training, size_t *bytes_out);
+/* coeffs_out = g .* coeffs for every detail subband, lowpass copied;
+ * gains_dev [B][R][dims] float32 (lowpass slot untouched) may be NULL.       */
+int sl_cnn_apply(const sl_system *s, const float *params_dev, const void *packed_dev,
+                 const float *coeffs_dev, const float *sigma_dev, int batch,
+                 float *coeffs_out_dev, float *gains_dev, void *workspace_dev,
+                 size_t workspace_bytes, void *stream);
+/* Gradient of a loss with respect to params_dev, given dL/d(coeffs_out)
+ * (dcoeffs_dev, [B][R][dims] float32) and the input coefficients:
+ * grads_dev [J][SL_CNN_PARAMS] float32 (overwritten).  Recomputes the
+ * forward pass; deterministic.                                              */
+int sl_cnn_backward(const sl_system *s, const float *params_dev, const void *packed_dev,
+                    const float *coeffs_dev, const float *sigma_dev, int batch,
+                    const float *dcoeffs_dev, float *grads_dev, void *workspace_dev,
+                    size_t workspace_bytes, void *stream);
+/* One Adam step (Kingma and Ba; beta1 0.9, beta2 0.999, eps 1e-8) on n
+ * float32 parameters with moment buffers m_dev, v_dev; step counts from 1.   */
+int sl_cnn_adam(float *params_dev, const float *grads_dev, float *m_dev, float *v_dev, int n,
+                float lr, int step, void *stream);
+/* out = scale * (a - b) over n floats and loss_dev[0] = sum (a - b)^2 (a
+ * fixed-order reduction): the gradient of a squared-error image loss.
+ * loss_dev must hold SL_SQERR_SCRATCH floats (the rest is scratch).          */
+#define SL_SQERR_SCRATCH 1025
+int sl_sq_error_grad(const float *a_dev, const float *b_dev, size_t n, float scale,
+                     float *out_dev, float *loss_dev, void *stream);
+
 /* ---- diagnostics: per-pass device timing ---------------------------------
  * When enabled, every kernel launch of the transforms is bracketed by a pair
  * of HIP events recorded on the launch stream; sl_timing_query synchronises

@@ -69,6 +69,23 @@ _SIGS = {
     "sl_denoise": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                     ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+    "sl_inverse_adjoint": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                            ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+    "sl_cnn_packed_bytes": ([ctypes.c_int], ctypes.c_size_t),
+    "sl_cnn_pack": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p],
+                    ctypes.c_int),
+    "sl_cnn_workspace_size": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                               ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "sl_cnn_apply": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                      ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                      ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+    "sl_cnn_backward": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                         ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+    "sl_cnn_adam": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                     ctypes.c_int, ctypes.c_float, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "sl_sq_error_grad": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_float,
+                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "sl_timing_enable": ([ctypes.c_int], ctypes.c_int),
     "sl_timing_reset": ([], ctypes.c_int),
     "sl_timing_num_passes": ([], ctypes.c_int),
@@ -264,6 +281,17 @@ class System:
                                _ptr(out), _ptr(ws), ws.numel(), _stream()))
         return out
 
+    def inverse_adjoint(self, r, coeffs=None, workspace=None):
+        """Adjoint of the inverse: forward transform with the dual filters."""
+        import torch
+        B = r.shape[0]
+        if coeffs is None:
+            coeffs = torch.empty((B, self.R, *self.dims), dtype=torch.float32, device=r.device)
+        ws = workspace if workspace is not None else self.workspace(B, r.device)
+        check(lib().sl_inverse_adjoint(self._h, _ptr(r), B, _ptr(coeffs), _ptr(ws), ws.numel(),
+                                       _stream()))
+        return coeffs
+
     def denoise(self, x, sigma, K, coeffs=None, scales=None, out=None, workspace=None):
         import torch
         self._check_x(x)
@@ -278,3 +306,73 @@ class System:
                                _ptr(coeffs), _ptr(scales), _ptr(out), _ptr(ws), ws.numel(),
                                _stream()))
         return out
+
+
+CNN_PARAMS = 10145
+SQERR_SCRATCH = 1025
+
+
+class Shrinkage:
+    """Per-scale learned shrinkage network bound to a 2D system.
+
+    params holds the FP32 master copy [J, CNN_PARAMS]; the matrix-core
+    kernels read the bfloat16 operand pack rebuilt by pack()."""
+
+    def __init__(self, system, params):
+        import torch
+        self.sys = system
+        self.J = system.n_scales
+        self.params = params.contiguous()
+        assert self.params.shape == (self.J, CNN_PARAMS) and self.params.dtype == torch.float32
+        n = lib().sl_cnn_packed_bytes(self.J)
+        self.packed = torch.empty(n, dtype=torch.uint8, device=params.device)
+        self._ws = {}
+        self.pack()
+
+    def pack(self):
+        check(lib().sl_cnn_pack(_ptr(self.params), self.J, _ptr(self.packed), _stream()))
+
+    def _workspace(self, B, training, device):
+        import torch
+        n = ctypes.c_size_t()
+        check(lib().sl_cnn_workspace_size(self.sys._h, int(B), int(training), ctypes.byref(n)))
+        key = (int(training), str(device))
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < n.value:
+            ws = torch.empty(n.value, dtype=torch.uint8, device=device)
+            self._ws[key] = ws
+        return ws
+
+    def apply(self, coeffs, sigma, out=None, gains=None):
+        import torch
+        B = coeffs.shape[0]
+        if out is None:
+            out = torch.empty_like(coeffs)
+        ws = self._workspace(B, False, coeffs.device)
+        check(lib().sl_cnn_apply(self.sys._h, _ptr(self.params), _ptr(self.packed), _ptr(coeffs),
+                                 _ptr(sigma), B, _ptr(out), _ptr(gains), _ptr(ws), ws.numel(),
+                                 _stream()))
+        return out
+
+    def backward(self, coeffs, sigma, dcoeffs, grads=None):
+        import torch
+        B = coeffs.shape[0]
+        if grads is None:
+            grads = torch.empty_like(self.params)
+        ws = self._workspace(B, True, coeffs.device)
+        check(lib().sl_cnn_backward(self.sys._h, _ptr(self.params), _ptr(self.packed),
+                                    _ptr(coeffs), _ptr(sigma), B, _ptr(dcoeffs), _ptr(grads),
+                                    _ptr(ws), ws.numel(), _stream()))
+        return grads
+
+
+def adam_step(params, grads, m, v, lr, step):
+    check(lib().sl_cnn_adam(_ptr(params), _ptr(grads), _ptr(m), _ptr(v), params.numel(),
+                            float(lr), int(step), _stream()))
+
+
+def sq_error_grad(a, b, scale, out, scratch):
+    """out = scale (a - b); scratch[0] = sum (a - b)^2 (scratch >= SQERR_SCRATCH floats)."""
+    check(lib().sl_sq_error_grad(_ptr(a), _ptr(b), a.numel(), float(scale), _ptr(out),
+                                 _ptr(scratch), _stream()))
+    return out

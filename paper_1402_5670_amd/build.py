@@ -16,7 +16,8 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libshearlet.so")
 
-SOURCES = ["api.cpp", "host_filters.cpp", "kernels2d.hip", "kernels3d.hip"]
+SOURCES = ["api.cpp", "host_filters.cpp", "kernels2d.hip", "kernels3d.hip", "cnn.hip",
+           "cnn_api.cpp"]
 
 ARCH = os.environ.get("SL_OFFLOAD_ARCH", "gfx950")
 

@@ -13,6 +13,7 @@
 #include "../../include/shearlet.h"
 #include "dispatch.hpp"
 #include "host_filters.hpp"
+#include "system.hpp"
 
 namespace {
 
@@ -32,22 +33,10 @@ size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
 }  // namespace
 
-struct sl_system {
-  slh::Config cfg;
-  std::vector<slh::Subband> subs;
-  std::vector<double> l2, l1;
-  int R = 0;
-  int device = 0;
-  size_t chunk_cap = 0;
-  float *d_filt = nullptr;    // 2D: [R][H][W]
-  float *d_psi = nullptr;     // Psi_hat on the grid
-  float *d_l2 = nullptr, *d_l1 = nullptr;
-  int *d_jof = nullptr;
-  sl::Sub3D *d_subs3 = nullptr;   // 3D: per-subband factor descriptors
-  float *d_tab3 = nullptr;        // 3D: factor tables
-  std::map<int, float2 *> d_tw;
-  std::vector<void *> allocs;
-};
+namespace sl {
+size_t transform_workspace_bytes(const sl_system *s, int batch);
+}
+
 
 namespace {
 
@@ -225,7 +214,7 @@ hipError_t timed(int pass, hipStream_t st, F &&launch) {
 #define SL_LAUNCH(pass, st, expr) SL_TRY(timed(pass, st, [&]() { return (expr); }))
 
 int forward3d(const sl_system *s, const float *x, int batch, void *coef, float *scales,
-              float2 *F, float2 *T, unsigned *xmax, hipStream_t st) {
+              float2 *F, float2 *T, unsigned *xmax, bool dual, hipStream_t st) {
   const int D = (int)s->cfg.dims[0], H = (int)s->cfg.dims[1], W = (int)s->cfg.dims[2];
   const bool scaled = s->cfg.dtype != SL_F32;
   const sl::Sys2D vr = view2d(s, D * H, W, 0, W);       // x lines
@@ -236,6 +225,7 @@ int forward3d(const sl_system *s, const float *x, int batch, void *coef, float *
   SL_LAUNCH(P_ROWS_REAL_FFT, st, sl::launch_rows_real_fft(vr, x, F, scaled ? xmax : nullptr, batch, st));
   SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, F, F, batch * D, false, st));
   SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vz, F, F, batch, false, st));
+  if (dual) SL_LAUNCH(P_AUX, st, sl::launch_div_psi(F, s->d_psi, (size_t)s->cfg.npix(), batch, st));
   if (scaled) SL_LAUNCH(P_AUX, st, sl::launch_scales(vr, xmax, scales, batch, st));
   int nb, np;
   chunk_plan(s, batch, nb, np);
@@ -273,6 +263,13 @@ int inverse3d(const sl_system *s, const void *coef, const float *scales, int bat
 }
 
 }  // namespace
+
+int sl::set_error(int code, const std::string &msg) { return fail(code, msg); }
+int sl::hip_error(hipError_t e, const char *what) { return hip_fail(e, what); }
+
+size_t sl::transform_workspace_bytes(const sl_system *s, int batch) {
+  return layout(s, batch).total;
+}
 
 extern "C" {
 
@@ -440,8 +437,9 @@ int sl_workspace_size(const sl_system *s, int batch, size_t *bytes_out) {
   return SL_OK;
 }
 
-int sl_forward(const sl_system *s, const float *x_dev, int batch, void *coeffs_dev,
-               float *scales_dev, void *workspace_dev, size_t workspace_bytes, void *stream) {
+static int forward_impl(const sl_system *s, const float *x_dev, int batch, void *coeffs_dev,
+                        float *scales_dev, void *workspace_dev, size_t workspace_bytes,
+                        void *stream, bool dual) {
   int rc = check_call(s, batch, x_dev, coeffs_dev, workspace_dev, workspace_bytes);
   if (rc) return rc;
   const bool scaled = s->cfg.dtype != SL_F32;
@@ -452,11 +450,13 @@ int sl_forward(const sl_system *s, const float *x_dev, int batch, void *coeffs_d
   float2 *F = (float2 *)(ws + L.off_F);
   float2 *T = (float2 *)(ws + L.off_chunk);
   unsigned *xmax = (unsigned *)(ws + L.off_xmax);
-  if (s->cfg.ndim == 3) return forward3d(s, x_dev, batch, coeffs_dev, scales_dev, F, T, xmax, st);
+  if (s->cfg.ndim == 3)
+    return forward3d(s, x_dev, batch, coeffs_dev, scales_dev, F, T, xmax, dual, st);
   const sl::Sys2D v = view2d(s);
   if (scaled) SL_LAUNCH(P_AUX, st, sl::launch_zero_u32(xmax, batch, st));
   SL_LAUNCH(P_ROWS_REAL_FFT, st, sl::launch_rows_real_fft(v, x_dev, F, scaled ? xmax : nullptr, batch, st));
   SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(v, F, F, batch, false, st));
+  if (dual) SL_LAUNCH(P_AUX, st, sl::launch_div_psi(F, s->d_psi, (size_t)s->cfg.npix(), batch, st));
   if (scaled) SL_LAUNCH(P_AUX, st, sl::launch_scales(v, xmax, scales_dev, batch, st));
   int nb, np;
   chunk_plan(s, batch, nb, np);
@@ -468,6 +468,19 @@ int sl_forward(const sl_system *s, const float *x_dev, int batch, void *coeffs_d
       SL_LAUNCH(P_ROWS_COEF, st, sl::launch_rows_coef(v, T, coeffs_dev, scales_dev, c, st));
     }
   return SL_OK;
+}
+
+int sl_forward(const sl_system *s, const float *x_dev, int batch, void *coeffs_dev,
+               float *scales_dev, void *workspace_dev, size_t workspace_bytes, void *stream) {
+  return forward_impl(s, x_dev, batch, coeffs_dev, scales_dev, workspace_dev, workspace_bytes,
+                      stream, false);
+}
+
+int sl_inverse_adjoint(const sl_system *s, const float *r_dev, int batch, float *coeffs_dev,
+                       void *workspace_dev, size_t workspace_bytes, void *stream) {
+  if (s && s->cfg.dtype != SL_F32) return fail(SL_EINVAL, "the adjoint needs SL_F32 storage");
+  return forward_impl(s, r_dev, batch, coeffs_dev, nullptr, workspace_dev, workspace_bytes,
+                      stream, true);
 }
 
 int sl_inverse(const sl_system *s, const void *coeffs_dev, const float *scales_dev, int batch,

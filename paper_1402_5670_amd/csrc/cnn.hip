@@ -1,0 +1,431 @@
+// Learned shrinkage network on gfx950 matrix cores (an extension beyond the
+// paper: a per-scale CNN predicting a gain in [0, 1] for every detail
+// coefficient; hard thresholding, Section 5.3, is its fallback).
+//
+//   x0 = (|c| / (sigma ||psi_i||_2), sigma * 255 / 50)        2 channels
+//   h1 = relu(conv3x3(x0; W1) + b1)     h2 = relu(conv3x3(h1; W2) + b2)
+//   g  = sigmoid(conv3x3(h2; W3) + b3)  shrunk coefficient g * c
+//
+// Activations are channel-last bfloat16 tensors [P][H][W][32] (P planes, 64 B
+// per pixel, unused channels zero).  A 3x3 convolution is an implicit GEMM:
+// for every tap, 16 output pixels x 16 output channels accumulate one
+// v_mfma_f32_16x16x32_bf16 over the 32 input channels (FP32 accumulation).
+// Operand layout of that instruction (64 lanes, l = lane):
+//   A[m][k]: m = l % 16, k = 8 (l / 16) + j, j = 0..7  (8 bf16 per lane)
+//   B[k][n]: n = l % 16, k = 8 (l / 16) + j
+//   D[m][n]: n = l % 16, m = 4 (l / 16) + i, i = 0..3  (4 floats per lane)
+// The backward data pass is the same convolution with flipped, transposed
+// weights; weight gradients put pixels on the reduction axis.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "cnn.hpp"
+
+namespace sl {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int TH = 8, TW = 32;                 // output tile
+constexpr int HH = TH + 2, HW2 = TW + 2;       // input halo tile
+constexpr int CH = 32;
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);             // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// ---------------------------------------------------------------------------
+// x0 planes from the coefficients
+// ---------------------------------------------------------------------------
+__global__ void k_cnn_x0(const float *__restrict__ coef, CnnPlanes pl, uint16_t *__restrict__ x0,
+                         int HWn) {
+  const int p = blockIdx.y;
+  const int px = blockIdx.x * blockDim.x + threadIdx.x;
+  if (px >= HWn) return;
+  int b, i, j;
+  plane_info(pl, p, b, i, j);
+  const float sg = pl.sigma[b];
+  const float c = coef[((size_t)b * pl.R + i) * HWn + px];
+  const float v0 = fabsf(c) / (sg * pl.l2[i]);
+  const float v1 = sg * (255.0f / 50.0f);
+  uint4 *dst = (uint4 *)(x0 + ((size_t)p * HWn + px) * CH);
+  dst[0] = make_uint4((uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16), 0u, 0u, 0u);
+  dst[1] = make_uint4(0u, 0u, 0u, 0u);
+  dst[2] = make_uint4(0u, 0u, 0u, 0u);
+  dst[3] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 convolution, implicit GEMM on MFMA
+// ---------------------------------------------------------------------------
+// Wp: packed B operands [J][9][NB][64 lanes][8] bf16; bias [J][..] float
+template <int NB, int MODE>
+__global__ void __launch_bounds__(256)
+k_conv3x3(const uint16_t *__restrict__ in, const uint16_t *__restrict__ Wp,
+          const float *__restrict__ bias, int bias_stride, CnnPlanes pl, int H, int W,
+          uint16_t *__restrict__ out, const uint16_t *__restrict__ mask,
+          const float *__restrict__ coef, float *__restrict__ coef_out, float *__restrict__ gain) {
+  __shared__ __attribute__((aligned(16))) uint16_t tile[HH * HW2 * CH];
+  const int p = blockIdx.z;
+  const int ty0 = blockIdx.y * TH, tx0 = blockIdx.x * TW;
+  const size_t HWn = (size_t)H * W;
+  const uint16_t *src = in + (size_t)p * HWn * CH;
+  int b, i, j;
+  plane_info(pl, p, b, i, j);
+  // halo tile: 16-byte chunks, zero outside the image
+  for (int q = threadIdx.x; q < HH * HW2 * 4; q += 256) {
+    const int pix = q >> 2, part = q & 3;
+    const int yy = ty0 + pix / HW2 - 1, xx = tx0 + pix % HW2 - 1;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+      v = ((const uint4 *)(src + ((size_t)yy * W + xx) * CH))[part];
+    ((uint4 *)tile)[q] = v;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  bf16x8 wb[9][NB];
+  const uint16_t *wj = Wp + (size_t)j * 9 * NB * 64 * 8;
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+      wb[t][nb] = *(const bf16x8 *)(wj + (((size_t)t * NB + nb) * 64 + lane) * 8);
+  __syncthreads();
+  // 16 pixel blocks (row r, half h) per tile; wave w takes blocks w, w+4, w+8, w+12
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int blk = wave + 4 * s;
+    const int r = blk >> 1, c0 = (blk & 1) * 16;
+    f32x4 acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int dy = t / 3, dx = t % 3;
+      const int pix = (r + dy) * HW2 + c0 + (lane & 15) + dx;
+      const bf16x8 a = *(const bf16x8 *)(tile + pix * CH + 8 * (lane >> 4));
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wb[t][nb], acc[nb], 0, 0, 0);
+    }
+    // epilogue: lane holds pixels m = 4 (lane / 16) + e of the block, channel lane % 16
+    const int yy = ty0 + r;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int xx = tx0 + c0 + 4 * (lane >> 4) + e;
+      if (yy >= H || xx >= W) continue;
+      const size_t opix = (size_t)p * HWn + (size_t)yy * W + xx;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int ch = 16 * nb + (lane & 15);
+        float v = acc[nb][e];
+        if constexpr (MODE == CONV_RELU) {
+          v += bias[(size_t)j * bias_stride + ch];
+          out[opix * CH + ch] = v > 0.f ? f2bf(v) : (uint16_t)0;
+        } else if constexpr (MODE == CONV_MASKED) {
+          out[opix * CH + ch] = mask[opix * CH + ch] != 0 ? f2bf(v) : (uint16_t)0;
+        } else {   // CONV_GAIN: channel 0 only
+          if (ch == 0) {
+            v += bias[(size_t)j * bias_stride];
+            const float g = 1.0f / (1.0f + __expf(-v));
+            const size_t co = ((size_t)b * pl.R + i) * HWn + (size_t)yy * W + xx;
+            if (gain) gain[co] = g;
+            if (coef_out) coef_out[co] = g * coef[co];
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// backward helpers
+// ---------------------------------------------------------------------------
+// dz = dL/dc' * c * g (1 - g) on channel 0 of a zero-padded bf16 tensor;
+// dbias3 partial sums are reduced later from dzf (float copy).
+__global__ void k_cnn_dz(const float *__restrict__ dcoef, const float *__restrict__ coef,
+                         const float *__restrict__ gain, CnnPlanes pl, int HWn,
+                         uint16_t *__restrict__ dz, float *__restrict__ dzf) {
+  const int p = blockIdx.y;
+  const int px = blockIdx.x * blockDim.x + threadIdx.x;
+  if (px >= HWn) return;
+  int b, i, j;
+  plane_info(pl, p, b, i, j);
+  const size_t co = ((size_t)b * pl.R + i) * HWn + px;
+  const size_t o = (size_t)p * HWn + px;
+  const float g = gain[co];
+  const float v = dcoef[co] * coef[co] * g * (1.f - g);
+  if (dzf) dzf[o] = v;
+  uint4 *dst = (uint4 *)(dz + o * CH);
+  dst[0] = make_uint4((uint32_t)f2bf(v), 0u, 0u, 0u);
+  dst[1] = make_uint4(0u, 0u, 0u, 0u);
+  dst[2] = make_uint4(0u, 0u, 0u, 0u);
+  dst[3] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// Weight gradients dW[t][ci][co] = sum_p x[p + t - 1][ci] dy[p][co] and
+// db[co] = sum_p dy[p][co] over the tiles of planes of one scale.  Each block
+// walks tiles with a grid stride and writes one partial [9*32*32 + 32].
+// Pixels are the reduction axis: A[m = ci][k = pixel], B[k = pixel][n = co].
+__global__ void __launch_bounds__(256)
+k_conv_wgrad(const uint16_t *__restrict__ x, const uint16_t *__restrict__ dy, int H, int W,
+             int plane0, int nplanes, float *__restrict__ partial) {
+  __shared__ __attribute__((aligned(16))) uint16_t xs[CH][HH * HW2 + 8];
+  __shared__ __attribute__((aligned(16))) uint16_t ds[CH][TH * TW];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const size_t HWn = (size_t)H * W;
+  // wave w owns (tap, mb, nb) triples w, w + 4, ..., 36 in all
+  f32x4 acc[9];
+#pragma unroll
+  for (int s = 0; s < 9; ++s) acc[s] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float dbias = 0.f;
+  const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + TH - 1) / TH;
+  const int ntiles = nplanes * tiles_x * tiles_y;
+  for (int q = blockIdx.x; q < ntiles; q += gridDim.x) {
+    const int tid = q;
+    const int p = plane0 + tid / (tiles_x * tiles_y);
+    const int rem = tid % (tiles_x * tiles_y);
+    const int ty0 = (rem / tiles_x) * TH, tx0 = (rem % tiles_x) * TW;
+    __syncthreads();
+    for (int k = threadIdx.x; k < HH * HW2; k += 256) {
+      const int yy = ty0 + k / HW2 - 1, xx = tx0 + k % HW2 - 1;
+      const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
+      const uint16_t *s = x + ((size_t)p * HWn + (in ? (size_t)yy * W + xx : 0)) * CH;
+#pragma unroll
+      for (int c = 0; c < CH; ++c) xs[c][k] = in ? s[c] : (uint16_t)0;
+    }
+    for (int k = threadIdx.x; k < TH * TW; k += 256) {
+      const int yy = ty0 + k / TW, xx = tx0 + k % TW;
+      const bool in = yy < H && xx < W;
+      const uint16_t *s = dy + ((size_t)p * HWn + (in ? (size_t)yy * W + xx : 0)) * CH;
+#pragma unroll
+      for (int c = 0; c < CH; ++c) ds[c][k] = in ? s[c] : (uint16_t)0;
+    }
+    __syncthreads();
+    if (threadIdx.x < CH)
+      for (int k = 0; k < TH * TW; ++k) dbias += bf2f(ds[threadIdx.x][k]);
+#pragma unroll
+    for (int s = 0; s < 9; ++s) {
+      const int trip = wave + 4 * s;          // 0..35
+      const int t = trip >> 2, mb = (trip >> 1) & 1, nb = trip & 1;
+      const int dyy = t / 3, dxx = t % 3;
+      const int ci = 16 * mb + (lane & 15), co = 16 * nb + (lane & 15);
+      for (int r = 0; r < TH; ++r) {
+        uint16_t av[8];
+        const uint16_t *xa = &xs[ci][(r + dyy) * HW2 + dxx + 8 * (lane >> 4)];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) av[e] = xa[e];
+        const bf16x8 a = *(const bf16x8 *)av;
+        const bf16x8 bb = *(const bf16x8 *)&ds[co][r * TW + 8 * (lane >> 4)];
+        acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc[s], 0, 0, 0);
+      }
+    }
+  }
+  // D[m = ci][n = co]: lane holds ci = 16 mb + 4 (lane / 16) + e, co = 16 nb + lane % 16
+  float *dst = partial + (size_t)blockIdx.x * (9 * CH * CH + CH);
+#pragma unroll
+  for (int s = 0; s < 9; ++s) {
+    const int trip = wave + 4 * s;
+    const int t = trip >> 2, mb = (trip >> 1) & 1, nb = trip & 1;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int ci = 16 * mb + 4 * (lane >> 4) + e, co = 16 * nb + (lane & 15);
+      dst[(t * CH + ci) * CH + co] = acc[s][e];
+    }
+  }
+  if (threadIdx.x < CH) dst[9 * CH * CH + threadIdx.x] = dbias;
+}
+
+// Sum block partials in a fixed order (deterministic).
+__global__ void k_reduce_partials(const float *__restrict__ partial, int nparts, int len,
+                                  float *__restrict__ outv) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= len) return;
+  float s = 0.f;
+  for (int q = 0; q < nparts; ++q) s += partial[(size_t)q * len + k];
+  outv[k] = s;
+}
+
+// Pack the conv B operands of every scale from the FP32 parameter blobs.
+// mode 0: forward layer (W[co][ci][t]); mode 1: transposed layer with flipped
+// taps (W'[ci][co][8 - t]) for the backward data pass.
+__global__ void k_pack(const float *__restrict__ params, int J, int layer, int mode,
+                       uint16_t *__restrict__ Wp, int NB) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;   // over J*9*NB*64*8
+  const int total = J * 9 * NB * 64 * 8;
+  if (idx >= total) return;
+  const int jj = idx % 8, lane = (idx / 8) % 64, nb = (idx / 512) % NB, t = (idx / (512 * NB)) % 9;
+  const int js = idx / (512 * NB * 9);
+  const int n = 16 * nb + (lane & 15);          // output channel of this conv
+  const int k = 8 * (lane >> 4) + jj;           // input channel of this conv
+  const float *P = params + (size_t)js * kCnnParams;
+  float v = 0.f;
+  // forward weight of the requested layer: Wl[co][ci][t] with sizes (cout, cin)
+  const int off[3] = {kOffW1, kOffW2, kOffW3};
+  const int cin[3] = {2, 32, 32}, cout[3] = {32, 32, 1};
+  const int l = layer - 1;
+  if (mode == 0) {
+    if (n < cout[l] && k < cin[l]) v = P[off[l] + (n * cin[l] + k) * 9 + t];
+  } else {
+    // transposed: this conv maps the layer's output channels (k) to its input channels (n)
+    if (n < cin[l] && k < cout[l]) v = P[off[l] + (k * cin[l] + n) * 9 + (8 - t)];
+  }
+  Wp[idx] = f2bf(v);
+}
+
+// Adam (Kingma and Ba) on the FP32 master parameters.
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, int n, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const float gg = g[k];
+  const float mm = b1 * m[k] + (1.f - b1) * gg;
+  const float vv = b2 * v[k] + (1.f - b2) * gg * gg;
+  m[k] = mm;
+  v[k] = vv;
+  p[k] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t cnn_x0(const float *coef, const CnnPlanes &pl, int P, int H, int W, uint16_t *x0,
+                  hipStream_t st) {
+  const int HWn = H * W;
+  hipLaunchKernelGGL(k_cnn_x0, dim3((HWn + 255) / 256, P), dim3(256), 0, st, coef, pl, x0, HWn);
+  return hipGetLastError();
+}
+
+hipError_t cnn_conv(const uint16_t *in, const uint16_t *Wp, int NB, const float *bias,
+                    int bias_stride, const CnnPlanes &pl, int P, int H, int W, int mode,
+                    uint16_t *out, const uint16_t *mask, const float *coef, float *coef_out,
+                    float *gain, hipStream_t st) {
+  dim3 grid((W + TW - 1) / TW, (H + TH - 1) / TH, P);
+  if (mode == CONV_RELU && NB == 2)
+    hipLaunchKernelGGL((k_conv3x3<2, CONV_RELU>), grid, dim3(256), 0, st, in, Wp, bias,
+                       bias_stride, pl, H, W, out, mask, coef, coef_out, gain);
+  else if (mode == CONV_MASKED && NB == 2)
+    hipLaunchKernelGGL((k_conv3x3<2, CONV_MASKED>), grid, dim3(256), 0, st, in, Wp, bias,
+                       bias_stride, pl, H, W, out, mask, coef, coef_out, gain);
+  else if (mode == CONV_GAIN && NB == 1)
+    hipLaunchKernelGGL((k_conv3x3<1, CONV_GAIN>), grid, dim3(256), 0, st, in, Wp, bias,
+                       bias_stride, pl, H, W, out, mask, coef, coef_out, gain);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t cnn_dz(const float *dcoef, const float *coef, const float *gain, const CnnPlanes &pl,
+                  int P, int H, int W, uint16_t *dz, float *dzf, hipStream_t st) {
+  const int HWn = H * W;
+  hipLaunchKernelGGL(k_cnn_dz, dim3((HWn + 255) / 256, P), dim3(256), 0, st, dcoef, coef, gain,
+                     pl, HWn, dz, dzf);
+  return hipGetLastError();
+}
+
+hipError_t cnn_wgrad(const uint16_t *x, const uint16_t *dy, int H, int W, int plane0,
+                     int nplanes, int nblocks, float *partial, float *outv, hipStream_t st) {
+  hipLaunchKernelGGL(k_conv_wgrad, dim3(nblocks), dim3(256), 0, st, x, dy, H, W, plane0, nplanes,
+                     partial);
+  const int len = 9 * CH * CH + CH;
+  hipLaunchKernelGGL(k_reduce_partials, dim3((len + 255) / 256), dim3(256), 0, st, partial,
+                     nblocks, len, outv);
+  return hipGetLastError();
+}
+
+__global__ void k_copy_lowpass(const float *__restrict__ coef, float *__restrict__ out, int R,
+                               int HWn) {
+  const int b = blockIdx.y;
+  const int px = blockIdx.x * blockDim.x + threadIdx.x;
+  if (px < HWn) out[(size_t)b * R * HWn + px] = coef[(size_t)b * R * HWn + px];
+}
+
+// out = scale (a - b); partial[block] = sum of (a - b)^2 over the block's stride
+__global__ void k_sqerr(const float *__restrict__ a, const float *__restrict__ b, size_t n,
+                        float scale, float *__restrict__ out, float *__restrict__ partial) {
+  __shared__ float red[256];
+  float s = 0.f;
+  for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (size_t)gridDim.x * 256) {
+    const float d = a[k] - b[k];
+    out[k] = scale * d;
+    s += d * d;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+hipError_t sq_error_grad(const float *a, const float *b, size_t n, float scale, float *out,
+                         float *partial, int nblocks, float *loss, hipStream_t st) {
+  hipLaunchKernelGGL(k_sqerr, dim3(nblocks), dim3(256), 0, st, a, b, n, scale, out, partial);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, st, partial, nblocks, 1, loss);
+  return hipGetLastError();
+}
+
+hipError_t cnn_copy_lowpass(const float *coef, float *coef_out, int B, int R, int HWn,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_lowpass, dim3((HWn + 255) / 256, B), dim3(256), 0, st, coef, coef_out,
+                     R, HWn);
+  return hipGetLastError();
+}
+
+// Scatter the full [9][32][32] + [32] weight gradients of the three layers
+// into the parameter-blob layout of scale j (grads [J][kCnnParams]).
+// dW1 comes from x = x0 (ci < 2), dW3 from dy = dz (co = 0).
+__global__ void k_grad_assemble(const float *__restrict__ g1, const float *__restrict__ g2,
+                                const float *__restrict__ g3, int j, float *__restrict__ grads) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= kCnnParams) return;
+  constexpr int L = 9 * CH * CH;   // bias sums follow the weights
+  float v;
+  if (k < kOffB1) {            // W1[co][ci][t], ci < 2: full[t][ci][co] of layer 1
+    const int co = k / 18, ci = (k / 9) % 2, t = k % 9;
+    v = g1[(t * CH + ci) * CH + co];
+  } else if (k < kOffW2) {
+    v = g1[L + (k - kOffB1)];
+  } else if (k < kOffB2) {
+    const int q = k - kOffW2, co = q / 288, ci = (q / 9) % 32, t = q % 9;
+    v = g2[(t * CH + ci) * CH + co];
+  } else if (k < kOffW3) {
+    v = g2[L + (k - kOffB2)];
+  } else if (k < kOffB3) {     // W3[0][ci][t]
+    const int q = k - kOffW3, ci = q / 9, t = q % 9;
+    v = g3[(t * CH + ci) * CH + 0];
+  } else {
+    v = g3[L + 0];
+  }
+  grads[(size_t)j * kCnnParams + k] = v;
+}
+
+hipError_t cnn_grad_assemble(const float *dW1, const float *dW2, const float *dW3, int j,
+                             float *grads, hipStream_t st) {
+  hipLaunchKernelGGL(k_grad_assemble, dim3((kCnnParams + 255) / 256), dim3(256), 0, st, dW1, dW2,
+                     dW3, j, grads);
+  return hipGetLastError();
+}
+
+hipError_t cnn_pack(const float *params, int J, int layer, int mode, uint16_t *Wp, int NB,
+                    hipStream_t st) {
+  const int total = J * 9 * NB * 64 * 8;
+  hipLaunchKernelGGL(k_pack, dim3((total + 255) / 256), dim3(256), 0, st, params, J, layer, mode,
+                     Wp, NB);
+  return hipGetLastError();
+}
+
+hipError_t cnn_adam(float *p, const float *g, float *m, float *v, int n, float lr, float b1,
+                    float b2, float eps, int t, hipStream_t st) {
+  const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+  hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, st, p, g, m, v, n, lr, b1, b2,
+                     eps, c1, c2);
+  return hipGetLastError();
+}
+
+}  // namespace sl

@@ -51,6 +51,7 @@ hipError_t launch_rows_coef(const Sys2D &s, const float2 *T, void *coef, const f
 hipError_t launch_scales(const Sys2D &s, const unsigned *xmax, float *scales, int B,
                          hipStream_t st);
 hipError_t launch_zero_u32(unsigned *p, int n, hipStream_t st);
+hipError_t launch_div_psi(float2 *F, const float *psi, size_t npix, int B, hipStream_t st);
 
 // Inverse passes --------------------------------------------------------------
 // coefficients -> U[chunk] (decode, threshold, pair pack, row DFT)

@@ -201,6 +201,16 @@ __global__ void k_scales(const unsigned *__restrict__ xmax, const float *__restr
   scales[i] = bound > 0.f ? exp2f(ceilf(log2f(bound)) - 15.f) : 1.f;
 }
 
+// F[b][p] /= Psi_hat[p]: turns the forward transform into the adjoint of the
+// inverse (dual filters psi_hat_i / Psi_hat, eq. dual_filter).
+__global__ void k_div_psi(float2 *__restrict__ F, const float *__restrict__ psi, size_t npix) {
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= npix) return;
+  const float d = psi[k];
+  float2 *f = F + (size_t)blockIdx.y * npix + k;
+  *f = make_float2(f->x / d, f->y / d);
+}
+
 __global__ void k_zero_u32(unsigned *p, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -435,6 +445,12 @@ hipError_t launch_scales(const Sys2D &s, const unsigned *xmax, float *scales, in
                          hipStream_t st) {
   int n = B * s.R;
   hipLaunchKernelGGL(k_scales, dim3((n + 255) / 256), dim3(256), 0, st, xmax, s.l1, scales, B, s.R);
+  return hipGetLastError();
+}
+
+hipError_t launch_div_psi(float2 *F, const float *psi, size_t npix, int B, hipStream_t st) {
+  hipLaunchKernelGGL(k_div_psi, dim3((unsigned)((npix + 255) / 256), B), dim3(256), 0, st, F, psi,
+                     npix);
   return hipGetLastError();
 }
 

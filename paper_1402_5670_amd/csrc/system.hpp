@@ -1,0 +1,37 @@
+// Library-owned state of a shearlet system (internal to libshearlet).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <vector>
+
+#include "dispatch.hpp"
+#include "host_filters.hpp"
+
+struct sl_system {
+  slh::Config cfg;
+  std::vector<slh::Subband> subs;
+  std::vector<double> l2, l1;
+  int R = 0;
+  int device = 0;
+  size_t chunk_cap = 0;
+  float *d_filt = nullptr;    // 2D: [R][H][W]
+  float *d_psi = nullptr;     // Psi_hat on the grid
+  float *d_l2 = nullptr, *d_l1 = nullptr;
+  int *d_jof = nullptr;
+  sl::Sub3D *d_subs3 = nullptr;   // 3D: per-subband factor descriptors
+  float *d_tab3 = nullptr;        // 3D: factor tables
+  std::map<int, float2 *> d_tw;
+  std::vector<void *> allocs;
+};
+
+#include <string>
+
+namespace sl {
+// workspace layout shared by the transforms and the CNN calls
+size_t transform_workspace_bytes(const sl_system *s, int batch);
+// record an error message for sl_last_error and return code
+int set_error(int code, const std::string &msg);
+int hip_error(hipError_t e, const char *what);
+}

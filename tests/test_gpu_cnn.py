@@ -1,0 +1,162 @@
+"""GPU checks of the learned-shrinkage kernels (MFMA, bfloat16 operands,
+float32 accumulation) against the FP64 oracle with bfloat16 emulation, and
+of the transform adjoint used to back-propagate an image-domain loss.
+
+Tolerances: gains and gradients relative L2 <= 1e-3 (the oracle rounds the
+same operands to bfloat16; what remains is float32-vs-float64 accumulation
+order, which can flip an occasional bfloat16 rounding of an activation);
+adjoint relative L2 <= 1e-5 (float32 transform)."""
+import numpy as np
+import pytest
+
+from oracle import cnn as OC
+from oracle import system as S
+from oracle import transform as T
+from paper_1402_5670_amd import synthetic as syn
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1402_5670_amd import binding as B  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel())
+
+
+def _gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(DEV)
+
+
+def blob(p):
+    return np.concatenate([p["W1"].ravel(), p["b1"], p["W2"].ravel(), p["b2"], p["W3"].ravel(),
+                           p["b3"]])
+
+
+def unblob(v):
+    v = np.asarray(v, dtype=np.float64)
+    return {"W1": v[0:576].reshape(32, 2, 3, 3), "b1": v[576:608],
+            "W2": v[608:9824].reshape(32, 32, 3, 3), "b2": v[9824:9856],
+            "W3": v[9856:10144].reshape(1, 32, 3, 3), "b3": v[10144:10145]}
+
+
+def _setup(dims=(64, 64), J=2, levels=(1, 1), Bn=2, seed=0):
+    sysg = B.System(dims, J, levels)
+    sig = np.array([0.05 + 0.05 * b for b in range(Bn)], dtype=np.float32)
+    xs = np.stack([syn.noisy_cartoon2d(*dims, 100 + b, float(sig[b]))[1] for b in range(Bn)])
+    c, _ = sysg.forward(_gpu(xs))
+    torch.cuda.synchronize()
+    params = []
+    for j in range(J):
+        p = OC.init_params(32, seed=seed + j)
+        rng = np.random.default_rng(seed + 10 + j)
+        for k in ("b1", "b2", "b3"):
+            p[k] = rng.standard_normal(p[k].shape) * 0.1
+        params.append(p)
+    pg = _gpu(np.stack([blob(p) for p in params]))
+    return sysg, sig, c, params, pg
+
+
+def test_inverse_adjoint():
+    print("case: adjoint 64x48 J=2 d=[1,1] B=2", flush=True)
+    dims = (64, 48)
+    sysg = B.System(dims, 2, [1, 1])
+    o = S.build_2d(dims, 2, [1, 1])
+    rng = np.random.default_rng(4)
+    r = rng.standard_normal((2, *dims))
+    c = rng.standard_normal((2, sysg.R, *dims))
+    a = sysg.inverse_adjoint(_gpu(r))
+    x = sysg.inverse(_gpu(c))
+    torch.cuda.synchronize()
+    an = a.cpu().numpy().astype(np.float64)
+    for b in range(2):
+        R = np.fft.fft2(r[b]) / o.dual_weight
+        ref = np.stack([np.fft.ifft2(R * f).real for f in o.filters])
+        assert rel(an[b], ref) < 1e-5
+    lhs = np.sum(x.cpu().numpy().astype(np.float64) * r)
+    rhs = np.sum(c * an)
+    assert abs(lhs - rhs) < 1e-5 * np.linalg.norm(c) * np.linalg.norm(an)
+
+
+def test_cnn_forward_matches_oracle():
+    print("case: cnn apply 64x64 J=2 B=2 (32 planes)", flush=True)
+    sysg, sig, c, params, pg = _setup()
+    net = B.Shrinkage(sysg, pg)
+    gains = torch.zeros_like(c)
+    out = net.apply(c, _gpu(sig), gains=gains)
+    torch.cuda.synchronize()
+    cn = c.cpu().numpy().astype(np.float64)
+    gn = gains.cpu().numpy()
+    on = out.cpu().numpy()
+    assert np.array_equal(on[:, 0], c.cpu().numpy()[:, 0])        # lowpass copied
+    l2 = np.array([s[4] for s in sysg.subbands], dtype=np.float32)
+    num = den = 0.0
+    for b in range(c.shape[0]):
+        for i in range(1, sysg.R):
+            j = sysg.subbands[i][1]
+            g, _ = OC.forward(params[j], cn[b, i], float(sig[b]), float(l2[i]), bf16=True)
+            num += np.sum((gn[b, i] - g) ** 2)
+            den += np.sum(g ** 2)
+            assert np.allclose(on[b, i], gn[b, i] * cn[b, i], rtol=1e-6, atol=1e-7)
+    assert np.sqrt(num / den) < 1e-3
+
+
+def test_cnn_backward_matches_oracle():
+    print("case: cnn backward 64x64 J=2 B=2", flush=True)
+    sysg, sig, c, params, pg = _setup(seed=3)
+    net = B.Shrinkage(sysg, pg)
+    rng = np.random.default_rng(7)
+    dc = rng.standard_normal(tuple(c.shape)).astype(np.float32)
+    grads = net.backward(c, _gpu(sig), _gpu(dc))
+    torch.cuda.synchronize()
+    gg = grads.cpu().numpy()
+    cn = c.cpu().numpy().astype(np.float64)
+    l2 = np.array([s[4] for s in sysg.subbands], dtype=np.float32)
+    ref = [{k: np.zeros_like(v) for k, v in params[j].items()} for j in range(sysg.n_scales)]
+    for b in range(c.shape[0]):
+        for i in range(1, sysg.R):
+            j = sysg.subbands[i][1]
+            g, cache = OC.forward(params[j], cn[b, i], float(sig[b]), float(l2[i]), bf16=True)
+            gr = OC.backward(cache, dc[b, i].astype(np.float64) * cn[b, i])
+            for k in gr:
+                ref[j][k] += gr[k]
+    for j in range(sysg.n_scales):
+        got = unblob(gg[j])
+        for k in ref[j]:
+            assert rel(got[k], ref[j][k]) < 1e-3, (j, k, rel(got[k], ref[j][k]))
+
+
+def test_training_reduces_loss():
+    # a few Adam steps on one batch: the image-domain loss must go down
+    print("case: cnn training smoke 64x64", flush=True)
+    sysg, sig, c, params, pg = _setup(seed=5)
+    dims = sysg.dims
+    clean = np.stack([syn.cartoon2d(*dims, 100 + b) for b in range(2)])
+    cg = _gpu(clean)
+    net = B.Shrinkage(sysg, pg)
+    m = torch.zeros_like(pg)
+    v = torch.zeros_like(pg)
+    scratch = torch.zeros(B.SQERR_SCRATCH, dtype=torch.float32, device=DEV)
+    sg = _gpu(sig)
+    losses = []
+    n = clean.size
+    for step in range(1, 31):
+        shrunk = net.apply(c, sg)
+        xh = sysg.inverse(shrunk)
+        r = torch.empty_like(xh)
+        B.sq_error_grad(xh, cg, 2.0 / n, r, scratch)
+        dc = sysg.inverse_adjoint(r)
+        grads = net.backward(c, sg, dc)
+        B.adam_step(net.params, grads, m, v, 2e-3, step)
+        net.pack()
+        torch.cuda.synchronize()
+        losses.append(float(scratch[0].item()) / n)
+    assert losses[-1] < 0.9 * losses[0], losses
+    assert np.isfinite(losses).all()
