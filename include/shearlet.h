@@ -144,6 +144,44 @@ int sl_denoise(const sl_system *s, const float *x_dev, int batch, const float *s
 int sl_inverse_adjoint(const sl_system *s, const float *r_dev, int batch, float *coeffs_dev,
                        void *workspace_dev, size_t workspace_bytes, void *stream);
 
+/* Bytes of the intermediate chunk of subband-pair planes that one pass
+ * launch processes (default 128 MiB or $SL_CHUNK_MB).  Changing it changes
+ * sl_workspace_size.                                                        */
+int sl_system_set_chunk_bytes(sl_system *s, size_t bytes);
+size_t sl_system_chunk_bytes(const sl_system *s);
+
+/* ---- uneven batches (several image sizes in one schedule) ----------------
+ * A multi-batch groups n_classes size classes: class s has its own system
+ * (not owned; must outlive the multi-batch) and counts[s] images stored
+ * contiguously ([counts[s]][dims_s]).  The buffer arguments below are arrays
+ * of n_classes device pointers, one per class.  what: 1 = forward,
+ * 2 = inverse (hard threshold if sigma_dev is not NULL: per class [counts]),
+ * 3 = both.  One workspace of sl_multi_workspace_size bytes serves all
+ * classes (disjoint slots, so classes may run concurrently).               */
+typedef struct sl_multi sl_multi;
+int sl_multi_create(sl_system *const *systems, const int *counts, int n_classes,
+                    sl_multi **out);
+void sl_multi_free(sl_multi *m);
+int sl_multi_workspace_size(sl_multi *m, size_t *bytes_out);
+int sl_multi_run(sl_multi *m, int what, const float *const *x_dev, void *const *coeffs_dev,
+                 float *const *scales_dev, const float *const *sigma_dev, const float *K_host,
+                 float *const *out_dev, void *workspace_dev, size_t workspace_bytes,
+                 void *stream);
+/* Times forward + inverse for each class at chunk sizes of 16..256 MiB that
+ * fit the class's current workspace slot and keeps the fastest (cached by
+ * size, R, batch and storage type in the text file cache_path, if given).  */
+int sl_multi_autotune(sl_multi *m, const float *const *x_dev, void *const *coeffs_dev,
+                      float *const *scales_dev, float *const *out_dev, void *workspace_dev,
+                      size_t workspace_bytes, const char *cache_path, void *stream);
+/* Captures one run (same arguments as sl_multi_run) into a HIP graph with
+ * one branch per class; sl_multi_graph_launch replays it on a stream.  The
+ * buffers are baked into the graph.  Per-pass timing must be off.          */
+int sl_multi_graph_build(sl_multi *m, int what, const float *const *x_dev,
+                         void *const *coeffs_dev, float *const *scales_dev,
+                         const float *const *sigma_dev, const float *K_host,
+                         float *const *out_dev, void *workspace_dev, size_t workspace_bytes);
+int sl_multi_graph_launch(sl_multi *m, void *stream);
+
 /* ---- learned shrinkage (an extension beyond the paper) -------------------
  * A per-scale CNN maps each detail coefficient plane c (with the noise level
  * sigma of its image) to gains g in [0, 1]:
@@ -184,6 +222,17 @@ int sl_cnn_adam(float *params_dev, const float *grads_dev, float *m_dev, float *
 #define SL_SQERR_SCRATCH 1025
 int sl_sq_error_grad(const float *a_dev, const float *b_dev, size_t n, float scale,
                      float *out_dev, float *loss_dev, void *stream);
+
+/* ---- training-data synthesis (not part of the paper's method) -----------
+ * Renders n cartoon images [n][H][W] float32: shapes_dev is the packed shape
+ * table [n][1 + max_shapes * 24] (background, then per shape: type 0/1/2,
+ * value, ellipse cx cy a b cos sin | polygon count and up to 8 vertices),
+ * painted in order with membership tested at pixel centres.  If noisy_dev
+ * is not NULL it receives clean + sigma[n] * N(0,1) noise from a
+ * counter-based generator keyed by (noise_seed, image, pixel).              */
+int sl_render_cartoons(const float *shapes_dev, int n, int H, int W, int max_shapes,
+                       const float *sigma_dev, uint64_t noise_seed, float *clean_dev,
+                       float *noisy_dev, void *stream);
 
 /* ---- diagnostics: per-pass device timing ---------------------------------
  * When enabled, every kernel launch of the transforms is bracketed by a pair

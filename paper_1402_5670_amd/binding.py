@@ -86,6 +86,23 @@ _SIGS = {
                      ctypes.c_int, ctypes.c_float, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "sl_sq_error_grad": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_float,
                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "sl_render_cartoons": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                            ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                            ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "sl_system_set_chunk_bytes": ([ctypes.c_void_p, ctypes.c_size_t], ctypes.c_int),
+    "sl_system_chunk_bytes": ([ctypes.c_void_p], ctypes.c_size_t),
+    "sl_multi_create": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                         ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "sl_multi_free": ([ctypes.c_void_p], None),
+    "sl_multi_workspace_size": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "sl_multi_run": ([ctypes.c_void_p, ctypes.c_int] + [ctypes.c_void_p] * 6 +
+                     [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+    "sl_multi_autotune": ([ctypes.c_void_p] + [ctypes.c_void_p] * 4 +
+                          [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_char_p, ctypes.c_void_p],
+                          ctypes.c_int),
+    "sl_multi_graph_build": ([ctypes.c_void_p, ctypes.c_int] + [ctypes.c_void_p] * 6 +
+                             [ctypes.c_void_p, ctypes.c_size_t], ctypes.c_int),
+    "sl_multi_graph_launch": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "sl_timing_enable": ([ctypes.c_int], ctypes.c_int),
     "sl_timing_reset": ([], ctypes.c_int),
     "sl_timing_num_passes": ([], ctypes.c_int),
@@ -376,3 +393,72 @@ def sq_error_grad(a, b, scale, out, scratch):
     check(lib().sl_sq_error_grad(_ptr(a), _ptr(b), a.numel(), float(scale), _ptr(out),
                                  _ptr(scratch), _stream()))
     return out
+
+
+def render_cartoons(shapes, H, W, sigma, noise_seed, clean, noisy=None):
+    """Rasterise packed shape tables ([n, 1 + 16 * 24] float32 on the device)."""
+    n = shapes.shape[0]
+    max_shapes = (shapes.shape[1] - 1) // 24
+    check(lib().sl_render_cartoons(_ptr(shapes), n, H, W, max_shapes, _ptr(sigma),
+                                   int(noise_seed) & 0xFFFFFFFFFFFFFFFF, _ptr(clean), _ptr(noisy),
+                                   _stream()))
+    return clean, noisy
+
+
+def _ptr_array(tensors):
+    arr = (ctypes.c_void_p * len(tensors))(*[0 if t is None else t.data_ptr() for t in tensors])
+    return arr
+
+
+class Multi:
+    """Uneven batch: one system per size class, images of a class contiguous."""
+
+    def __init__(self, systems, counts):
+        self.systems = list(systems)
+        self.counts = [int(c) for c in counts]
+        h = ctypes.c_void_p()
+        sysarr = (ctypes.c_void_p * len(systems))(*[s._h.value for s in systems])
+        cnt = (ctypes.c_int * len(counts))(*self.counts)
+        check(lib().sl_multi_create(sysarr, cnt, len(systems), ctypes.byref(h)))
+        self._h = h
+        self._keep = []
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.sl_multi_free(h)
+            self._h = None
+
+    def workspace_bytes(self):
+        n = ctypes.c_size_t()
+        check(lib().sl_multi_workspace_size(self._h, ctypes.byref(n)))
+        return n.value
+
+    def _args(self, xs, coeffs, scales, sigmas, K, outs):
+        arrs = [_ptr_array(xs), _ptr_array(coeffs),
+                _ptr_array(scales) if scales is not None else None,
+                _ptr_array(sigmas) if sigmas is not None else None,
+                (ctypes.c_float * len(K))(*[float(k) for k in K]) if K is not None else None,
+                _ptr_array(outs) if outs is not None else None]
+        self._keep.append(arrs)
+        return [ctypes.cast(a, ctypes.c_void_p) if a is not None else None for a in arrs]
+
+    def run(self, what, xs, coeffs, scales=None, sigmas=None, K=None, outs=None, workspace=None):
+        a = self._args(xs, coeffs, scales, sigmas, K, outs)
+        check(lib().sl_multi_run(self._h, int(what), *a, _ptr(workspace), workspace.numel(),
+                                 _stream()))
+
+    def autotune(self, xs, coeffs, scales, outs, workspace, cache_path=None):
+        a = self._args(xs, coeffs, scales, None, None, outs)
+        check(lib().sl_multi_autotune(self._h, a[0], a[1], a[2], a[5], _ptr(workspace),
+                                      workspace.numel(),
+                                      cache_path.encode() if cache_path else None, _stream()))
+
+    def graph_build(self, what, xs, coeffs, scales=None, sigmas=None, K=None, outs=None,
+                    workspace=None):
+        a = self._args(xs, coeffs, scales, sigmas, K, outs)
+        check(lib().sl_multi_graph_build(self._h, int(what), *a, _ptr(workspace),
+                                         workspace.numel()))
+
+    def graph_launch(self):
+        check(lib().sl_multi_graph_launch(self._h, _stream()))

@@ -10,6 +10,12 @@
 #include "cnn.hpp"
 #include "system.hpp"
 
+namespace sl {
+hipError_t render_cartoons(const float *shapes, int n, int H, int W, int max_shapes,
+                           const float *sigma, uint64_t seed, float *clean, float *noisy,
+                           hipStream_t st);
+}
+
 namespace {
 
 using sl::kCnnParams;
@@ -247,6 +253,17 @@ int sl_sq_error_grad(const float *a_dev, const float *b_dev, size_t n, float sca
   // loss_dev[1 .. SL_SQERR_SCRATCH) holds the per-block partial sums
   CK(sl::sq_error_grad(a_dev, b_dev, n, scale, out_dev, loss_dev + 1, kErrBlocks, loss_dev,
                        (hipStream_t)stream));
+  return SL_OK;
+}
+
+int sl_render_cartoons(const float *shapes_dev, int n, int H, int W, int max_shapes,
+                       const float *sigma_dev, uint64_t noise_seed, float *clean_dev,
+                       float *noisy_dev, void *stream) {
+  if (!shapes_dev || !clean_dev || n < 1 || n > 65535 || H < 1 || W < 1 || max_shapes < 0 ||
+      (noisy_dev && !sigma_dev))
+    return sl::set_error(SL_EINVAL, "bad arguments to sl_render_cartoons");
+  CK(sl::render_cartoons(shapes_dev, n, H, W, max_shapes, sigma_dev, noise_seed, clean_dev,
+                         noisy_dev, (hipStream_t)stream));
   return SL_OK;
 }
 

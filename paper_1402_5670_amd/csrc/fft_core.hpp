@@ -125,12 +125,21 @@ struct Plan {
   static_assert(pow2() * (N / pow2()) == N, "bad size");
 };
 
-// LDS addressing of line m: element n at base[n * LN + m * LM].
+// LDS addressing of one line.  Column tiles interleave M lines (element n of
+// line m at base[n * M + m], stride_n = M), which keeps the 64 lanes of a
+// wave on consecutive words.  Row tiles store a line contiguously with one
+// pad element after every 8 (stride_n = 0 selects that layout): without it
+// the radix-8 stage writes at stride 8 elements and 16 lanes share a bank.
 struct LdsLine {
   float2 *base;
   int stride_n;
-  __device__ __forceinline__ float2 &operator[](int n) const { return base[n * stride_n]; }
+  __device__ __forceinline__ float2 &operator[](int n) const {
+    return stride_n ? base[n * stride_n] : base[n + (n >> 3)];
+  }
 };
+// LDS elements of one padded row line of length N
+template <int N>
+constexpr int row_lds_len() { return N + N / 8; }
 
 template <int N, int S_, bool INV>
 __device__ __forceinline__ void fft_stage(float2 (&v)[Plan<N>::E], int t, const LdsLine &lds,

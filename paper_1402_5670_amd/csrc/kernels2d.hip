@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(Tile<N>::THREADS)
 k_rows_real_fft(const float *__restrict__ x, float2 *__restrict__ A, unsigned *__restrict__ xmax,
                 int H, const float2 *__restrict__ tw) {
   constexpr int NT = Tile<N>::NT, M = Tile<N>::M, E = Tile<N>::E;
-  __shared__ float2 lds[M * N];
+  __shared__ float2 lds[M * row_lds_len<N>()];
   const int t = threadIdx.x % NT, m = threadIdx.x / NT;
   const int row = blockIdx.x * M + m, b = blockIdx.y;
   const bool ok = row < H;
@@ -92,7 +92,7 @@ k_rows_real_fft(const float *__restrict__ x, float2 *__restrict__ A, unsigned *_
       atomicMax(xmax + b, __float_as_uint(amax));   // partial wave: no cross-lane reduction
     }
   }
-  fft_line<N, false>(v, t, LdsLine{lds + m * N, 1}, tw);
+  fft_line<N, false>(v, t, LdsLine{lds + m * row_lds_len<N>(), 0}, tw);
   if (ok) {
 #pragma unroll
     for (int e = 0; e < E; ++e) A[off + t + e * NT] = v[e];
@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(Tile<N>::THREADS)
 k_cols_fft(const float2 *__restrict__ A, float2 *__restrict__ F, int W,
            const float2 *__restrict__ tw) {
   constexpr int NT = Tile<N>::NT, M = Tile<N>::M, E = Tile<N>::E;
-  __shared__ float2 lds[M * N];
+  __shared__ float2 lds[M * row_lds_len<N>()];
   const int m = threadIdx.x % M, t = threadIdx.x / M;
   const int col = blockIdx.x * M + m;
   const bool ok = col < W;
@@ -125,7 +125,7 @@ k_cols_filter_ifft(const float2 *__restrict__ F, const float *__restrict__ filt,
                    float2 *__restrict__ T, int W, int R, int b0, int p0, int np,
                    const float2 *__restrict__ tw) {
   constexpr int NT = Tile<N>::NT, M = Tile<N>::M, E = Tile<N>::E;
-  __shared__ float2 lds[M * N];
+  __shared__ float2 lds[M * row_lds_len<N>()];
   const int m = threadIdx.x % M, t = threadIdx.x / M;
   const int col = blockIdx.x * M + m;
   const bool ok = col < W;
@@ -162,7 +162,7 @@ k_rows_coef(const float2 *__restrict__ T, typename Store<DT>::T *__restrict__ co
             const float *__restrict__ scales, int H, int R, int b0, int p0, int np, float inv_hw,
             const float2 *__restrict__ tw) {
   constexpr int NT = Tile<N>::NT, M = Tile<N>::M, E = Tile<N>::E;
-  __shared__ float2 lds[M * N];
+  __shared__ float2 lds[M * row_lds_len<N>()];
   const int t = threadIdx.x % NT, m = threadIdx.x / NT;
   const int row = blockIdx.x * M + m;
   const bool ok = row < H;
@@ -174,7 +174,7 @@ k_rows_coef(const float2 *__restrict__ T, typename Store<DT>::T *__restrict__ co
   float2 v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = Ti[t + e * NT];
-  fft_line<N, true>(v, t, LdsLine{lds + m * N, 1}, tw);
+  fft_line<N, true>(v, t, LdsLine{lds + m * row_lds_len<N>(), 0}, tw);
   if (!ok) return;
   float sa = inv_hw, sb = inv_hw;
   if (DT != 0) {
@@ -225,7 +225,7 @@ k_rows_coef_fft(const typename Store<DT>::T *__restrict__ coef, const float *__r
                 float2 *__restrict__ U, int H, int R, int b0, int p0, int np, ThrArgs thr,
                 const float2 *__restrict__ tw) {
   constexpr int NT = Tile<N>::NT, M = Tile<N>::M, E = Tile<N>::E;
-  __shared__ float2 lds[M * N];
+  __shared__ float2 lds[M * row_lds_len<N>()];
   const int t = threadIdx.x % NT, m = threadIdx.x / NT;
   const int row = blockIdx.x * M + m;
   const bool ok = row < H;
@@ -260,7 +260,7 @@ k_rows_coef_fft(const typename Store<DT>::T *__restrict__ coef, const float *__r
     if (!(fabsf(bb) >= db)) bb = 0.f;
     v[e] = make_float2(a, bb);
   }
-  fft_line<N, false>(v, t, LdsLine{lds + m * N, 1}, tw);
+  fft_line<N, false>(v, t, LdsLine{lds + m * row_lds_len<N>(), 0}, tw);
   if (ok) {
     float2 *Uo = U + ((size_t)bl * np + pp) * plane + (size_t)row * N;
 #pragma unroll
@@ -274,7 +274,7 @@ k_cols_fft_acc(const float2 *__restrict__ U, const float *__restrict__ filt,
                const float *__restrict__ psi, float2 *__restrict__ ACC, int W, int R, int b0,
                int p0, int np, int first, int last, const float2 *__restrict__ tw) {
   constexpr int NT = Tile<N>::NT, M = Tile<N>::M, E = Tile<N>::E;
-  __shared__ float2 lds[M * N];
+  __shared__ float2 lds[M * row_lds_len<N>()];
   const int m = threadIdx.x % M, t = threadIdx.x / M;
   const int col = blockIdx.x * M + m;
   const bool ok = col < W;
@@ -325,7 +325,7 @@ __global__ void __launch_bounds__(Tile<N>::THREADS)
 k_rows_real_ifft(const float2 *__restrict__ V, float *__restrict__ x, int H, float inv_hw,
                  const float2 *__restrict__ tw) {
   constexpr int NT = Tile<N>::NT, M = Tile<N>::M, E = Tile<N>::E;
-  __shared__ float2 lds[M * N];
+  __shared__ float2 lds[M * row_lds_len<N>()];
   const int t = threadIdx.x % NT, m = threadIdx.x / NT;
   const int row = blockIdx.x * M + m, b = blockIdx.y;
   const bool ok = row < H;
@@ -333,7 +333,7 @@ k_rows_real_ifft(const float2 *__restrict__ V, float *__restrict__ x, int H, flo
   float2 v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = V[off + t + e * NT];
-  fft_line<N, true>(v, t, LdsLine{lds + m * N, 1}, tw);
+  fft_line<N, true>(v, t, LdsLine{lds + m * row_lds_len<N>(), 0}, tw);
   if (ok) {
 #pragma unroll
     for (int e = 0; e < E; ++e) x[off + t + e * NT] = v[e].x * inv_hw;

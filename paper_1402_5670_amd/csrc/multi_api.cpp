@@ -1,0 +1,289 @@
+// Uneven batches: images of several sizes in one schedule (declared in
+// include/shearlet.h).  Each size class runs the batched passes of its own
+// system; the classes are independent, so a captured HIP graph forks one
+// branch per class and the GPU runs the branches concurrently.  An autotuner
+// picks each class's chunk size (the number of subband pairs per pass
+// launch, which trades launch count against Infinity Cache residency of the
+// intermediate) by timing the candidates on the caller's buffers; results
+// are cached in a small text file.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/shearlet.h"
+#include "system.hpp"
+
+struct sl_multi {
+  std::vector<sl_system *> sys;
+  std::vector<int> counts;
+  std::vector<size_t> ws_off;
+  size_t ws_total = 0;
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> join;
+  hipEvent_t fork = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+size_t al(size_t v) { return (v + 255) / 256 * 256; }
+
+void layout(sl_multi *m) {
+  m->ws_off.assign(m->sys.size(), 0);
+  size_t off = 0;
+  for (size_t s = 0; s < m->sys.size(); ++s) {
+    m->ws_off[s] = off;
+    size_t b = 0;
+    sl_workspace_size(m->sys[s], m->counts[s], &b);
+    off += al(b);
+  }
+  m->ws_total = off;
+}
+
+struct Bufs {
+  const float *const *x;
+  void *const *coeffs;
+  float *const *scales;
+  const float *const *sigma;
+  const float *K;
+  float *const *out;
+  char *ws;
+};
+
+int run_class(sl_multi *m, int s, const Bufs &b, int what, hipStream_t st) {
+  void *ws = b.ws + m->ws_off[s];
+  size_t wsb = 0;
+  sl_workspace_size(m->sys[s], m->counts[s], &wsb);
+  int rc = SL_OK;
+  if (what & 1)
+    rc = sl_forward(m->sys[s], b.x[s], m->counts[s], b.coeffs[s], b.scales ? b.scales[s] : nullptr,
+                    ws, wsb, st);
+  if (rc == SL_OK && (what & 2))
+    rc = sl_inverse(m->sys[s], b.coeffs[s], b.scales ? b.scales[s] : nullptr, m->counts[s],
+                    b.sigma ? b.sigma[s] : nullptr, b.K, b.out[s], ws, wsb, st);
+  return rc;
+}
+
+std::string tune_key(const sl_system *s, int count) {
+  std::ostringstream k;
+  k << s->cfg.ndim;
+  for (int i = 0; i < s->cfg.ndim; ++i) k << "x" << s->cfg.dims[i];
+  k << ":R" << s->R << ":B" << count << ":T" << s->cfg.dtype;
+  return k.str();
+}
+
+std::map<std::string, size_t> load_cache(const char *path) {
+  std::map<std::string, size_t> c;
+  if (!path) return c;
+  std::ifstream f(path);
+  std::string key;
+  size_t v;
+  while (f >> key >> v) c[key] = v;
+  return c;
+}
+
+void save_cache(const char *path, const std::map<std::string, size_t> &c) {
+  if (!path) return;
+  std::ofstream f(path);
+  for (auto &kv : c) f << kv.first << " " << kv.second << "\n";
+}
+
+#define CK(expr)                                            \
+  do {                                                      \
+    hipError_t e_ = (expr);                                 \
+    if (e_ != hipSuccess) return sl::hip_error(e_, #expr);  \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int sl_system_set_chunk_bytes(sl_system *s, size_t bytes) {
+  if (!s || bytes < (1u << 20)) return sl::set_error(SL_EINVAL, "chunk must be >= 1 MiB");
+  s->chunk_cap = bytes;
+  return SL_OK;
+}
+
+size_t sl_system_chunk_bytes(const sl_system *s) { return s ? s->chunk_cap : 0; }
+
+int sl_multi_create(sl_system *const *systems, const int *counts, int n_classes, sl_multi **out) {
+  if (!systems || !counts || !out || n_classes < 1 || n_classes > 64)
+    return sl::set_error(SL_EINVAL, "bad arguments to sl_multi_create");
+  *out = nullptr;
+  auto *m = new sl_multi();
+  for (int s = 0; s < n_classes; ++s) {
+    if (!systems[s] || counts[s] < 1) {
+      delete m;
+      return sl::set_error(SL_EINVAL, "every class needs a system and at least one image");
+    }
+    m->sys.push_back(systems[s]);
+    m->counts.push_back(counts[s]);
+  }
+  layout(m);
+  *out = m;
+  return SL_OK;
+}
+
+void sl_multi_free(sl_multi *m) {
+  if (!m) return;
+  if (m->exec) (void)hipGraphExecDestroy(m->exec);
+  if (m->graph) (void)hipGraphDestroy(m->graph);
+  for (auto st : m->side) (void)hipStreamDestroy(st);
+  for (auto e : m->join) (void)hipEventDestroy(e);
+  if (m->fork) (void)hipEventDestroy(m->fork);
+  delete m;
+}
+
+int sl_multi_workspace_size(sl_multi *m, size_t *bytes_out) {
+  if (!m || !bytes_out) return sl::set_error(SL_EINVAL, "NULL argument");
+  layout(m);
+  *bytes_out = m->ws_total;
+  return SL_OK;
+}
+
+int sl_multi_run(sl_multi *m, int what, const float *const *x_dev, void *const *coeffs_dev,
+                 float *const *scales_dev, const float *const *sigma_dev, const float *K_host,
+                 float *const *out_dev, void *workspace_dev, size_t workspace_bytes,
+                 void *stream) {
+  if (!m || !workspace_dev || (what & ~3) || !what) return sl::set_error(SL_EINVAL, "bad arguments");
+  layout(m);
+  if (workspace_bytes < m->ws_total) return sl::set_error(SL_ENOMEM, "workspace too small");
+  Bufs b{x_dev, coeffs_dev, scales_dev, sigma_dev, K_host, out_dev, (char *)workspace_dev};
+  for (size_t s = 0; s < m->sys.size(); ++s) {
+    int rc = run_class(m, (int)s, b, what, (hipStream_t)stream);
+    if (rc) return rc;
+  }
+  return SL_OK;
+}
+
+int sl_multi_autotune(sl_multi *m, const float *const *x_dev, void *const *coeffs_dev,
+                      float *const *scales_dev, float *const *out_dev, void *workspace_dev,
+                      size_t workspace_bytes, const char *cache_path, void *stream) {
+  if (!m || !workspace_dev) return sl::set_error(SL_EINVAL, "bad arguments");
+  hipStream_t st = (hipStream_t)stream;
+  auto cache = load_cache(cache_path);
+  static const size_t cand_mb[] = {16, 32, 64, 128, 256};
+  Bufs b{x_dev, coeffs_dev, scales_dev, nullptr, nullptr, out_dev, (char *)workspace_dev};
+  hipEvent_t e0, e1;
+  CK(hipEventCreate(&e0));
+  CK(hipEventCreate(&e1));
+  // the workspace was sized for the current chunks: only candidates that keep
+  // every class within its present slot are admissible
+  std::vector<size_t> slot(m->sys.size());
+  for (size_t s = 0; s < m->sys.size(); ++s) sl_workspace_size(m->sys[s], m->counts[s], &slot[s]);
+  int rc = SL_OK;
+  for (size_t s = 0; s < m->sys.size() && rc == SL_OK; ++s) {
+    const std::string key = tune_key(m->sys[s], m->counts[s]);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      size_t keep = m->sys[s]->chunk_cap;
+      m->sys[s]->chunk_cap = it->second;
+      size_t need = 0;
+      sl_workspace_size(m->sys[s], m->counts[s], &need);
+      if (need > slot[s]) m->sys[s]->chunk_cap = keep;
+      continue;
+    }
+    float best = 1e30f;
+    size_t best_cap = m->sys[s]->chunk_cap;
+    for (size_t mb : cand_mb) {
+      m->sys[s]->chunk_cap = mb << 20;
+      size_t need = 0;
+      sl_workspace_size(m->sys[s], m->counts[s], &need);
+      if (need > slot[s]) continue;
+      rc = run_class(m, (int)s, b, 3, st);                       // warm-up
+      if (rc) break;
+      (void)hipEventRecord(e0, st);
+      for (int r = 0; r < 3 && rc == SL_OK; ++r) rc = run_class(m, (int)s, b, 3, st);
+      (void)hipEventRecord(e1, st);
+      if (rc) break;
+      (void)hipEventSynchronize(e1);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) {
+        best = ms;
+        best_cap = mb << 20;
+      }
+    }
+    m->sys[s]->chunk_cap = best_cap;
+    cache[key] = best_cap;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  save_cache(cache_path, cache);
+  layout(m);
+  if (m->ws_total > workspace_bytes) return sl::set_error(SL_ENOMEM, "workspace too small");
+  return SL_OK;
+}
+
+int sl_multi_graph_build(sl_multi *m, int what, const float *const *x_dev,
+                         void *const *coeffs_dev, float *const *scales_dev,
+                         const float *const *sigma_dev, const float *K_host,
+                         float *const *out_dev, void *workspace_dev, size_t workspace_bytes) {
+  if (!m || !workspace_dev || (what & ~3) || !what) return sl::set_error(SL_EINVAL, "bad arguments");
+  layout(m);
+  if (workspace_bytes < m->ws_total) return sl::set_error(SL_ENOMEM, "workspace too small");
+  if (m->exec) {
+    (void)hipGraphExecDestroy(m->exec);
+    m->exec = nullptr;
+  }
+  if (m->graph) {
+    (void)hipGraphDestroy(m->graph);
+    m->graph = nullptr;
+  }
+  const int n = (int)m->sys.size();
+  while ((int)m->side.size() < n) {
+    hipStream_t st;
+    CK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    m->side.push_back(st);
+    hipEvent_t e;
+    CK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    m->join.push_back(e);
+  }
+  if (!m->fork) CK(hipEventCreateWithFlags(&m->fork, hipEventDisableTiming));
+  Bufs b{x_dev, coeffs_dev, scales_dev, sigma_dev, K_host, out_dev, (char *)workspace_dev};
+  hipStream_t cs = m->side[0];
+  int timing_was = 0;
+  (void)timing_was;
+  CK(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+  int rc = SL_OK;
+  hipError_t e = hipEventRecord(m->fork, cs);
+  for (int s = 1; s < n && e == hipSuccess; ++s) e = hipStreamWaitEvent(m->side[s], m->fork, 0);
+  for (int s = 0; s < n && e == hipSuccess && rc == SL_OK; ++s) {
+    rc = run_class(m, s, b, what, m->side[s]);
+    if (rc == SL_OK && s > 0) {
+      e = hipEventRecord(m->join[s], m->side[s]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(cs, m->join[s], 0);
+    }
+  }
+  hipGraph_t g = nullptr;
+  hipError_t ec = hipStreamEndCapture(cs, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return sl::hip_error(e, "graph capture");
+  }
+  if (ec != hipSuccess) return sl::hip_error(ec, "hipStreamEndCapture");
+  m->graph = g;
+  CK(hipGraphInstantiate(&m->exec, g, nullptr, nullptr, 0));
+  return SL_OK;
+}
+
+int sl_multi_graph_launch(sl_multi *m, void *stream) {
+  if (!m || !m->exec) return sl::set_error(SL_EINVAL, "no graph: call sl_multi_graph_build");
+  CK(hipGraphLaunch(m->exec, (hipStream_t)stream));
+  return SL_OK;
+}
+
+}  // extern "C"

@@ -36,30 +36,75 @@ def _inside_polygon(px, py, vx, vy):
     return inside
 
 
-def cartoon2d(H, W, seed):
+def cartoon2d_shapes(H, W, seed):
+    """Draw the background level and the shape list of one cartoon image.
+
+    Each shape is ("ellipse", value, cx, cy, a, b, theta) or
+    ("polygon", value, vx, vy) with vertices in pixel coordinates."""
     rng = np.random.default_rng(seed)
-    img = np.full((H, W), rng.uniform(0.0, 1.0))
-    yy, xx = np.meshgrid(np.arange(H) + 0.5, np.arange(W) + 0.5, indexing="ij")
+    background = rng.uniform(0.0, 1.0)
     m = float(min(H, W))
+    shapes = []
     for _ in range(int(rng.integers(8, 17))):
         val = rng.uniform(0.0, 1.0)
         if rng.uniform() < 0.5:
             cy, cx = rng.uniform(0, H), rng.uniform(0, W)
             a, b = rng.uniform(m / 32, m / 4, size=2)
             th = rng.uniform(0.0, np.pi)
-            dx, dy = xx - cx, yy - cy
-            u = dx * np.cos(th) + dy * np.sin(th)
-            v = -dx * np.sin(th) + dy * np.cos(th)
-            mask = (u / a) ** 2 + (v / b) ** 2 <= 1.0
+            shapes.append(("ellipse", val, cx, cy, a, b, th))
         else:
             cy, cx = rng.uniform(0, H), rng.uniform(0, W)
             nv = int(rng.integers(3, 9))
             ang = np.sort(rng.uniform(0.0, 2 * np.pi, size=nv))
             r = rng.uniform(m / 16, m / 4)
             rad = r * rng.uniform(0.5, 1.0, size=nv)
-            mask = _inside_polygon(xx, yy, cx + rad * np.cos(ang), cy + rad * np.sin(ang))
+            shapes.append(("polygon", val, cx + rad * np.cos(ang), cy + rad * np.sin(ang)))
+    return background, shapes
+
+
+def cartoon2d(H, W, seed):
+    background, shapes = cartoon2d_shapes(H, W, seed)
+    img = np.full((H, W), background)
+    yy, xx = np.meshgrid(np.arange(H) + 0.5, np.arange(W) + 0.5, indexing="ij")
+    for sh in shapes:
+        if sh[0] == "ellipse":
+            _, val, cx, cy, a, b, th = sh
+            dx, dy = xx - cx, yy - cy
+            u = dx * np.cos(th) + dy * np.sin(th)
+            v = -dx * np.sin(th) + dy * np.cos(th)
+            mask = (u / a) ** 2 + (v / b) ** 2 <= 1.0
+        else:
+            _, val, vx, vy = sh
+            mask = _inside_polygon(xx, yy, vx, vy)
         img[mask] = val
     return img
+
+
+SHAPE_RECORD = 24   # floats per shape in shape_table
+
+
+def shape_table(H, W, seeds, max_shapes=16):
+    """Pack the shapes of several images for a rasterizer:
+    float32 [n_images][1 + max_shapes * SHAPE_RECORD] with
+    [0] = background; per shape: type (0 none, 1 ellipse, 2 polygon), value,
+    ellipse: cx, cy, a, b, cos(theta), sin(theta);
+    polygon: n, then up to 8 (x, y) vertex pairs from offset 3."""
+    out = np.zeros((len(seeds), 1 + max_shapes * SHAPE_RECORD), dtype=np.float32)
+    for n, seed in enumerate(seeds):
+        bg, shapes = cartoon2d_shapes(H, W, seed)
+        out[n, 0] = bg
+        for k, sh in enumerate(shapes[:max_shapes]):
+            rec = out[n, 1 + k * SHAPE_RECORD:1 + (k + 1) * SHAPE_RECORD]
+            if sh[0] == "ellipse":
+                _, val, cx, cy, a, b, th = sh
+                rec[:8] = (1, val, cx, cy, a, b, np.cos(th), np.sin(th))
+            else:
+                _, val, vx, vy = sh
+                rec[0], rec[1], rec[2] = 2, val, len(vx)
+                for v in range(len(vx)):
+                    rec[3 + 2 * v] = vx[v]
+                    rec[4 + 2 * v] = vy[v]
+    return out
 
 
 def cartoon3d(D, H, W, seed):

@@ -120,17 +120,25 @@ def test_cnn_backward_matches_oracle():
     cn = c.cpu().numpy().astype(np.float64)
     l2 = np.array([s[4] for s in sysg.subbands], dtype=np.float32)
     ref = [{k: np.zeros_like(v) for k, v in params[j].items()} for j in range(sysg.n_scales)]
+    absdz = np.zeros(sysg.n_scales)
     for b in range(c.shape[0]):
         for i in range(1, sysg.R):
             j = sysg.subbands[i][1]
             g, cache = OC.forward(params[j], cn[b, i], float(sig[b]), float(l2[i]), bf16=True)
-            gr = OC.backward(cache, dc[b, i].astype(np.float64) * cn[b, i])
+            dg = dc[b, i].astype(np.float64) * cn[b, i]
+            gr = OC.backward(cache, dg)
+            absdz[j] += np.sum(np.abs(OC.bf16_round(dg * g * (1 - g))))
             for k in gr:
                 ref[j][k] += gr[k]
     for j in range(sysg.n_scales):
         got = unblob(gg[j])
         for k in ref[j]:
-            assert rel(got[k], ref[j][k]) < 1e-3, (j, k, rel(got[k], ref[j][k]))
+            if k == "b3":
+                # a scalar sum of +- bf16-rounded terms: bound the error by the sum of the
+                # terms' magnitudes (cancellation makes the plain relative error ill-posed)
+                assert abs(got[k][0] - ref[j][k][0]) < 1e-3 * absdz[j]
+            else:
+                assert rel(got[k], ref[j][k]) < 1e-3, (j, k, rel(got[k], ref[j][k]))
 
 
 def test_training_reduces_loss():

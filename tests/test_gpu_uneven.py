@@ -1,0 +1,98 @@
+"""Uneven batches: several image sizes in one schedule, eager and replayed
+from a HIP graph, against the FP64 oracle (FP16 coefficient storage,
+relative L2 <= 2e-3 per image) and the autotuner's cache."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import system as S
+from oracle import transform as T
+from paper_1402_5670_amd import synthetic as syn
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1402_5670_amd import binding as B  # noqa: E402
+
+DEV = torch.device("cuda:0")
+SIZES = [(64, 3), (96, 2), (128, 2), (256, 1)]
+J, LEVELS = 3, [1, 1, 2]
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel())
+
+
+def _setup(dtype="f16"):
+    systems, xs, coeffs, scales, outs, host = [], [], [], [], [], []
+    seed = 4001
+    for n, count in SIZES:
+        s = B.System((n, n), J, LEVELS, dtype=dtype)
+        imgs = np.stack([syn.noisy_cartoon2d(n, n, seed + k, 0.1)[1] for k in range(count)])
+        seed += count
+        host.append(imgs)
+        systems.append(s)
+        xs.append(torch.from_numpy(imgs.astype(np.float32)).to(DEV))
+        c, sc = s.alloc_coeffs(count, DEV)
+        coeffs.append(c)
+        scales.append(sc)
+        outs.append(torch.empty((count, n, n), device=DEV))
+    m = B.Multi(systems, [c for _, c in SIZES])
+    ws = torch.empty(m.workspace_bytes(), dtype=torch.uint8, device=DEV)
+    return m, systems, host, xs, coeffs, scales, outs, ws
+
+
+def _check(systems, host, coeffs, scales, outs, tol):
+    for s, imgs, c, sc, o in zip(systems, host, coeffs, scales, outs):
+        orc = S.build_2d(s.dims, J, LEVELS)
+        cd = c.float().cpu().numpy().astype(np.float64) * sc.cpu().numpy()[:, :, None, None]
+        for k in range(imgs.shape[0]):
+            assert rel(cd[k], T.forward(imgs[k], orc.filters)) < tol
+            assert rel(o[k].cpu().numpy(), imgs[k]) < tol
+
+
+def test_uneven_eager_and_graph():
+    print("case: uneven sizes 64x3 96x2 128x2 256x1, f16", flush=True)
+    m, systems, host, xs, coeffs, scales, outs, ws = _setup()
+    m.run(3, xs, coeffs, scales, outs=outs, workspace=ws)
+    torch.cuda.synchronize()
+    _check(systems, host, coeffs, scales, outs, 2e-3)
+    ref_c = [c.clone() for c in coeffs]
+    ref_o = [o.clone() for o in outs]
+    m.graph_build(3, xs, coeffs, scales, outs=outs, workspace=ws)
+    for rep in range(3):
+        for c in coeffs:
+            c.zero_()
+        for o in outs:
+            o.zero_()
+        torch.cuda.synchronize()
+        m.graph_launch()
+        torch.cuda.synchronize()
+        for a, b in zip(coeffs, ref_c):
+            assert torch.equal(a, b), rep
+        for a, b in zip(outs, ref_o):
+            assert torch.equal(a, b), rep
+        # eager work between replays
+        m.run(1, xs, coeffs, scales, workspace=ws)
+        torch.cuda.synchronize()
+
+
+def test_uneven_autotune(tmp_path):
+    print("case: uneven autotune", flush=True)
+    m, systems, host, xs, coeffs, scales, outs, ws = _setup()
+    cache = str(tmp_path / "tune.txt")
+    m.autotune(xs, coeffs, scales, outs, ws, cache_path=cache)
+    assert os.path.exists(cache)
+    lines = open(cache).read().split("\n")
+    assert len([ln for ln in lines if ln.strip()]) == len(SIZES)
+    m.run(3, xs, coeffs, scales, outs=outs, workspace=ws)
+    torch.cuda.synchronize()
+    _check(systems, host, coeffs, scales, outs, 2e-3)
+    # a second autotune reads the cache
+    m.autotune(xs, coeffs, scales, outs, ws, cache_path=cache)
