@@ -93,6 +93,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -201,6 +202,13 @@ def main():
         "passes": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in passes.items()},
         "roofline": roof,
     }
+    wpath = os.path.join(ROOT, "paper_1402_5670_amd", "weights", "shrinkage_512_J4.npz")
+    if not args.no_learned and os.path.exists(wpath):
+        # learned shrinkage vs hard thresholding at equal sigma, same GPU, held-out images
+        from paper_1402_5670_amd import train as TR
+        params = np.load(wpath)["params"]
+        ev = TR.evaluate(params, size=H, n_scales=J, shear_levels=levels, K=K, n_images=Bn)
+        res["learned"] = {k: round(v, 3) for k, v in ev.items()}
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args.cpu_seconds, sig, K, H, W, J, levels)
     print(json.dumps(res))

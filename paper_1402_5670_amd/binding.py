@@ -11,7 +11,8 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libshearlet.so")
+# SL_LIB may name an alternative build of the same library (same ABI)
+LIB_PATH = os.environ.get("SL_LIB") or os.path.join(_PKG, "libshearlet.so")
 
 SL_F32, SL_F16, SL_BF16 = 0, 1, 2
 _DTYPES = {"f32": SL_F32, "f16": SL_F16, "bf16": SL_BF16}

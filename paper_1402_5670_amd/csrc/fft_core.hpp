@@ -97,8 +97,9 @@ __device__ __forceinline__ void dft_r(float2 *x) {
 // ---------------------------------------------------------------------------
 // compile-time radix plans: 8s first, then a 4 or 2, then 3s
 // ---------------------------------------------------------------------------
-template <int N>
+template <int N_, int EMUL = 1>
 struct Plan {
+  static constexpr int N = N_;
   static constexpr int count3() { int n = N, c = 0; while (n % 3 == 0) { n /= 3; ++c; } return c; }
   static constexpr int pow2() { int n = N; while (n % 3 == 0) n /= 3; return n; }
   static constexpr int log2p() { int n = pow2(), c = 0; while (n > 1) { n /= 2; ++c; } return c; }
@@ -119,7 +120,7 @@ struct Plan {
     }
     return l;
   }
-  static constexpr int E = lcm_radix();     // values per thread
+  static constexpr int E = lcm_radix() * EMUL;   // values per thread
   static constexpr int NT = N / E;          // threads per line
   static constexpr int pbefore(int s) { int p = 1; for (int q = 0; q < s; ++q) p *= radix(q); return p; }
   static_assert(pow2() * (N / pow2()) == N, "bad size");
@@ -141,10 +142,10 @@ struct LdsLine {
 template <int N>
 constexpr int row_lds_len() { return N + N / 8; }
 
-template <int N, int S_, bool INV>
-__device__ __forceinline__ void fft_stage(float2 (&v)[Plan<N>::E], int t, const LdsLine &lds,
+template <class PL, int S_, bool INV>
+__device__ __forceinline__ void fft_stage(float2 (&v)[PL::E], int t, const LdsLine &lds,
                                           const float2 *__restrict__ tw) {
-  using PL = Plan<N>;
+  constexpr int N = PL::N;
   constexpr int E = PL::E, NT = PL::NT;
   constexpr int r = PL::radix(S_);
   constexpr int p = PL::pbefore(S_);
@@ -196,23 +197,29 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[Plan<N>::E], int t, const 
   }
 }
 
-template <int N, bool INV, int S_ = 0>
-__device__ __forceinline__ void fft_stages(float2 (&v)[Plan<N>::E], int t, const LdsLine &lds,
+template <class PL, bool INV, int S_ = 0>
+__device__ __forceinline__ void fft_stages(float2 (&v)[PL::E], int t, const LdsLine &lds,
                                            const float2 *__restrict__ tw) {
-  if constexpr (S_ < Plan<N>::S) {
-    fft_stage<N, S_, INV>(v, t, lds, tw);
-    fft_stages<N, INV, S_ + 1>(v, t, lds, tw);
+  if constexpr (S_ < PL::S) {
+    fft_stage<PL, S_, INV>(v, t, lds, tw);
+    fft_stages<PL, INV, S_ + 1>(v, t, lds, tw);
   }
 }
 
 // Full length-N FFT of one line held in registers (see file comment).  The
 // leading barrier makes it safe to call repeatedly on the same LDS buffer.
 // A single-stage plan never touches LDS.
+template <class PL, bool INV>
+__device__ __forceinline__ void fft_line_p(float2 (&v)[PL::E], int t, const LdsLine &lds,
+                                           const float2 *__restrict__ tw) {
+  if constexpr (PL::S > 1) __syncthreads();
+  fft_stages<PL, INV>(v, t, lds, tw);
+}
+
 template <int N, bool INV>
 __device__ __forceinline__ void fft_line(float2 (&v)[Plan<N>::E], int t, const LdsLine &lds,
                                          const float2 *__restrict__ tw) {
-  if constexpr (Plan<N>::S > 1) __syncthreads();
-  fft_stages<N, INV>(v, t, lds, tw);
+  fft_line_p<Plan<N>, INV>(v, t, lds, tw);
 }
 
 }  // namespace sl

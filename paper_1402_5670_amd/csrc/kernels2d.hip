@@ -25,11 +25,28 @@
 
 namespace sl {
 
+// Row tiles: M rows per block.  Column tiles: M adjacent columns per block;
+// with SL_COL_EMUL > 1 each thread of a column pass owns SL_COL_EMUL times
+// more values, halving the threads per column and doubling the columns per
+// block (wider coalesced segments) for lengths 256..512.
+#ifndef SL_COL_EMUL
+#define SL_COL_EMUL 1
+#endif
 template <int N>
 struct Tile {
-  static constexpr int NT = Plan<N>::NT;
-  static constexpr int E = Plan<N>::E;
+  using PL = Plan<N>;
+  static constexpr int NT = PL::NT;
+  static constexpr int E = PL::E;
   static constexpr int M = NT >= 128 ? 8 : 16;     // lines per block
+  static constexpr int THREADS = M * NT;
+};
+template <int N>
+struct CTile {
+  static constexpr int EM = (N >= 256 && N <= 512) ? SL_COL_EMUL : 1;
+  using PL = Plan<N, EM>;
+  static constexpr int NT = PL::NT;
+  static constexpr int E = PL::E;
+  static constexpr int M = (NT * 16 <= 1024 ? 16 : 8) * (EM > 1 ? 2 : 1);
   static constexpr int THREADS = M * NT;
 };
 
@@ -56,6 +73,23 @@ struct Store<2> {
   __device__ static T enc(float v) { return __float2bfloat16(v); }
   __device__ static float dec(T v) { return __bfloat162float(v); }
 };
+
+// Coefficient planes are streamed once per call; with SL_NT_COEF the float32
+// coefficient stores and loads carry the non-temporal hint so that they do
+// not displace the pass intermediates from the caches.
+#ifndef SL_NT_COEF
+#define SL_NT_COEF 0
+#endif
+template <class T>
+__device__ __forceinline__ void coef_store(T *p, T v) {
+  if constexpr (SL_NT_COEF && sizeof(T) == 4) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+template <class T>
+__device__ __forceinline__ T coef_load(const T *p) {
+  if constexpr (SL_NT_COEF && sizeof(T) == 4) return __builtin_nontemporal_load(p);
+  else return *p;
+}
 
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
@@ -100,11 +134,12 @@ k_rows_real_fft(const float *__restrict__ x, float2 *__restrict__ A, unsigned *_
 }
 
 template <int N, bool INV>
-__global__ void __launch_bounds__(Tile<N>::THREADS)
+__global__ void __launch_bounds__(CTile<N>::THREADS)
 k_cols_fft(const float2 *__restrict__ A, float2 *__restrict__ F, int W,
            const float2 *__restrict__ tw) {
-  constexpr int NT = Tile<N>::NT, M = Tile<N>::M, E = Tile<N>::E;
-  __shared__ float2 lds[M * row_lds_len<N>()];
+  constexpr int NT = CTile<N>::NT, M = CTile<N>::M, E = CTile<N>::E;
+  using PL = typename CTile<N>::PL;
+  __shared__ float2 lds[M * N];
   const int m = threadIdx.x % M, t = threadIdx.x / M;
   const int col = blockIdx.x * M + m;
   const bool ok = col < W;
@@ -112,46 +147,65 @@ k_cols_fft(const float2 *__restrict__ A, float2 *__restrict__ F, int W,
   float2 v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = ok ? A[base + (size_t)(t + e * NT) * W] : make_float2(0.f, 0.f);
-  fft_line<N, INV>(v, t, LdsLine{lds + m, M}, tw);
+  fft_line_p<PL, INV>(v, t, LdsLine{lds + m, M}, tw);
   if (ok) {
 #pragma unroll
     for (int e = 0; e < E; ++e) F[base + (size_t)(t + e * NT) * W] = v[e];
   }
 }
 
+// Images per column block: the filter pair tile is loaded once and applied
+// to SL_COL_BT images (fewer filter re-reads, more registers).
+#ifndef SL_COL_BT
+#define SL_COL_BT 1
+#endif
+
 template <int N>
-__global__ void __launch_bounds__(Tile<N>::THREADS)
+__global__ void __launch_bounds__(CTile<N>::THREADS)
 k_cols_filter_ifft(const float2 *__restrict__ F, const float *__restrict__ filt,
-                   float2 *__restrict__ T, int W, int R, int b0, int p0, int np,
+                   float2 *__restrict__ T, int W, int R, int b0, int nb, int p0, int np,
                    const float2 *__restrict__ tw) {
-  constexpr int NT = Tile<N>::NT, M = Tile<N>::M, E = Tile<N>::E;
-  __shared__ float2 lds[M * row_lds_len<N>()];
+  constexpr int NT = CTile<N>::NT, M = CTile<N>::M, E = CTile<N>::E, BT = SL_COL_BT;
+  using PL = typename CTile<N>::PL;
+  __shared__ float2 lds[M * N];
   const int m = threadIdx.x % M, t = threadIdx.x / M;
   const int col = blockIdx.x * M + m;
   const bool ok = col < W;
   const int cc = ok ? col : 0;
-  const int b = b0 + blockIdx.y;
   const size_t plane = (size_t)N * W;
-  float2 f[E];
+  float2 f[BT][E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) f[e] = F[(size_t)b * plane + (size_t)(t + e * NT) * W + cc];
+  for (int bt = 0; bt < BT; ++bt) {
+    const int bl = blockIdx.y * BT + bt;
+    const int b = b0 + (bl < nb ? bl : 0);
+#pragma unroll
+    for (int e = 0; e < E; ++e) f[bt][e] = F[(size_t)b * plane + (size_t)(t + e * NT) * W + cc];
+  }
   for (int pp = 0; pp < np; ++pp) {
     const int ia = 2 * (p0 + pp), ib = ia + 1;
     const float *fa = filt + (size_t)ia * plane + cc;
     const float *fb = filt + (size_t)(ib < R ? ib : ia) * plane + cc;
-    float2 v[E];
+    float a[E], bb[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const size_t o = (size_t)(t + e * NT) * W;
-      const float a = fa[o];
-      const float bb = ib < R ? fb[o] : 0.f;
-      v[e] = make_float2(f[e].x * a - f[e].y * bb, f[e].y * a + f[e].x * bb);
+      a[e] = fa[o];
+      bb[e] = ib < R ? fb[o] : 0.f;
     }
-    fft_line<N, true>(v, t, LdsLine{lds + m, M}, tw);
-    if (ok) {
-      float2 *To = T + ((size_t)blockIdx.y * np + pp) * plane + col;
 #pragma unroll
-      for (int e = 0; e < E; ++e) To[(size_t)(t + e * NT) * W] = v[e];
+    for (int bt = 0; bt < BT; ++bt) {
+      const int bl = blockIdx.y * BT + bt;
+      float2 v[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        v[e] = make_float2(f[bt][e].x * a[e] - f[bt][e].y * bb[e],
+                           f[bt][e].y * a[e] + f[bt][e].x * bb[e]);
+      fft_line_p<PL, true>(v, t, LdsLine{lds + m, M}, tw);
+      if (ok && bl < nb) {
+        float2 *To = T + ((size_t)bl * np + pp) * plane + col;
+#pragma unroll
+        for (int e = 0; e < E; ++e) To[(size_t)(t + e * NT) * W] = v[e];
+      }
     }
   }
 }
@@ -183,11 +237,11 @@ k_rows_coef(const float2 *__restrict__ T, typename Store<DT>::T *__restrict__ co
   }
   auto *ca = coef + ((size_t)b * R + ia) * plane + (size_t)row * N;
 #pragma unroll
-  for (int e = 0; e < E; ++e) ca[t + e * NT] = Store<DT>::enc(v[e].x * sa);
+  for (int e = 0; e < E; ++e) coef_store(ca + t + e * NT, Store<DT>::enc(v[e].x * sa));
   if (ib < R) {
     auto *cb = coef + ((size_t)b * R + ib) * plane + (size_t)row * N;
 #pragma unroll
-    for (int e = 0; e < E; ++e) cb[t + e * NT] = Store<DT>::enc(v[e].y * sb);
+    for (int e = 0; e < E; ++e) coef_store(cb + t + e * NT, Store<DT>::enc(v[e].y * sb));
   }
 }
 
@@ -254,8 +308,8 @@ k_rows_coef_fft(const typename Store<DT>::T *__restrict__ coef, const float *__r
   float2 v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    float a = Store<DT>::dec(ca[t + e * NT]) * sa;
-    float bb = has_b ? Store<DT>::dec(cb[t + e * NT]) * sb : 0.f;
+    float a = Store<DT>::dec(coef_load(ca + t + e * NT)) * sa;
+    float bb = has_b ? Store<DT>::dec(coef_load(cb + t + e * NT)) * sb : 0.f;
     if (!(fabsf(a) >= da)) a = 0.f;
     if (!(fabsf(bb) >= db)) bb = 0.f;
     v[e] = make_float2(a, bb);
@@ -269,54 +323,71 @@ k_rows_coef_fft(const typename Store<DT>::T *__restrict__ coef, const float *__r
 }
 
 template <int N>
-__global__ void __launch_bounds__(Tile<N>::THREADS)
+__global__ void __launch_bounds__(CTile<N>::THREADS)
 k_cols_fft_acc(const float2 *__restrict__ U, const float *__restrict__ filt,
                const float *__restrict__ psi, float2 *__restrict__ ACC, int W, int R, int b0,
-               int p0, int np, int first, int last, const float2 *__restrict__ tw) {
-  constexpr int NT = Tile<N>::NT, M = Tile<N>::M, E = Tile<N>::E;
-  __shared__ float2 lds[M * row_lds_len<N>()];
+               int nb, int p0, int np, int first, int last, const float2 *__restrict__ tw) {
+  constexpr int NT = CTile<N>::NT, M = CTile<N>::M, E = CTile<N>::E, BT = SL_COL_BT;
+  using PL = typename CTile<N>::PL;
+  __shared__ float2 lds[M * N];
   const int m = threadIdx.x % M, t = threadIdx.x / M;
   const int col = blockIdx.x * M + m;
   const bool ok = col < W;
   const int cc = ok ? col : 0;
-  const int b = b0 + blockIdx.y;
   const size_t plane = (size_t)N * W;
-  float2 *accp = ACC + (size_t)b * plane + cc;
-  float2 acc[E];
+  float2 acc[BT][E];
 #pragma unroll
-  for (int e = 0; e < E; ++e)
-    acc[e] = first ? make_float2(0.f, 0.f) : accp[(size_t)(t + e * NT) * W];
+  for (int bt = 0; bt < BT; ++bt) {
+    const int bl = blockIdx.y * BT + bt;
+    const float2 *accp = ACC + (size_t)(b0 + (bl < nb ? bl : 0)) * plane + cc;
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      acc[bt][e] = first ? make_float2(0.f, 0.f) : accp[(size_t)(t + e * NT) * W];
+  }
   for (int pp = 0; pp < np; ++pp) {
     const int ia = 2 * (p0 + pp), ib = ia + 1;
-    const float2 *Ui = U + ((size_t)blockIdx.y * np + pp) * plane + cc;
-    float2 v[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = Ui[(size_t)(t + e * NT) * W];
-    fft_line<N, false>(v, t, LdsLine{lds + m, M}, tw);
     const float *fa = filt + (size_t)ia * plane + cc;
     const float *fb = filt + (size_t)(ib < R ? ib : ia) * plane + cc;
+    float a[E], bb[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const size_t o = (size_t)(t + e * NT) * W;
-      const float a = fa[o];
-      const float bb = ib < R ? fb[o] : 0.f;
-      // (psi_a - i psi_b) * v
-      acc[e].x += a * v[e].x + bb * v[e].y;
-      acc[e].y += a * v[e].y - bb * v[e].x;
+      a[e] = fa[o];
+      bb[e] = ib < R ? fb[o] : 0.f;
+    }
+#pragma unroll
+    for (int bt = 0; bt < BT; ++bt) {
+      const int bl = blockIdx.y * BT + bt;
+      const float2 *Ui = U + ((size_t)(bl < nb ? bl : 0) * np + pp) * plane + cc;
+      float2 v[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = Ui[(size_t)(t + e * NT) * W];
+      fft_line_p<PL, false>(v, t, LdsLine{lds + m, M}, tw);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        // (psi_a - i psi_b) * v
+        acc[bt][e].x += a[e] * v[e].x + bb[e] * v[e].y;
+        acc[bt][e].y += a[e] * v[e].y - bb[e] * v[e].x;
+      }
     }
   }
-  if (last) {
-    const float *ps = psi + cc;
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const float d = ps[(size_t)(t + e * NT) * W];
-      acc[e] = make_float2(acc[e].x / d, acc[e].y / d);
+  for (int bt = 0; bt < BT; ++bt) {
+    const int bl = blockIdx.y * BT + bt;
+    if (last) {
+      const float *ps = psi + cc;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const float d = ps[(size_t)(t + e * NT) * W];
+        acc[bt][e] = make_float2(acc[bt][e].x / d, acc[bt][e].y / d);
+      }
+      fft_line_p<PL, true>(acc[bt], t, LdsLine{lds + m, M}, tw);
     }
-    fft_line<N, true>(acc, t, LdsLine{lds + m, M}, tw);
-  }
-  if (ok) {
+    if (ok && bl < nb) {
+      float2 *accp = ACC + (size_t)(b0 + bl) * plane + cc;
 #pragma unroll
-    for (int e = 0; e < E; ++e) accp[(size_t)(t + e * NT) * W] = acc[e];
+      for (int e = 0; e < E; ++e) accp[(size_t)(t + e * NT) * W] = acc[bt][e];
+    }
   }
 }
 
@@ -361,6 +432,10 @@ template <int N>
 static dim3 row_grid(int H, int y, int z = 1) {
   return dim3((H + Tile<N>::M - 1) / Tile<N>::M, y, z);
 }
+template <int N>
+static dim3 col_grid(int W, int y) {
+  return dim3((W + CTile<N>::M - 1) / CTile<N>::M, y, 1);
+}
 
 hipError_t launch_rows_real_fft(const Sys2D &s, const float *x, float2 *A, unsigned *xmax, int B,
                                 hipStream_t st) {
@@ -384,10 +459,10 @@ hipError_t launch_cols_fft(const Sys2D &s, const float2 *A, float2 *F, int B, bo
 #define X(N)                                                                                  \
   case N:                                                                                     \
     if (inverse)                                                                              \
-      hipLaunchKernelGGL((k_cols_fft<N, true>), row_grid<N>(s.W, B), dim3(Tile<N>::THREADS), 0, \
+      hipLaunchKernelGGL((k_cols_fft<N, true>), col_grid<N>(s.W, B), dim3(CTile<N>::THREADS), 0, \
                          st, A, F, s.W, s.twH);                                               \
     else                                                                                      \
-      hipLaunchKernelGGL((k_cols_fft<N, false>), row_grid<N>(s.W, B), dim3(Tile<N>::THREADS), \
+      hipLaunchKernelGGL((k_cols_fft<N, false>), col_grid<N>(s.W, B), dim3(CTile<N>::THREADS), \
                          0, st, A, F, s.W, s.twH);                                            \
     break;
     SL_FOR_EACH_N(X)
@@ -403,8 +478,9 @@ hipError_t launch_cols_filter_ifft(const Sys2D &s, const float2 *F, float2 *T, C
   switch (s.H) {
 #define X(N)                                                                                 \
   case N:                                                                                    \
-    hipLaunchKernelGGL(k_cols_filter_ifft<N>, row_grid<N>(s.W, c.nb), dim3(Tile<N>::THREADS), \
-                       0, st, F, s.filt, T, s.W, s.R, c.b0, c.p0, c.np, s.twH);              \
+    hipLaunchKernelGGL(k_cols_filter_ifft<N>, col_grid<N>(s.W, (c.nb + SL_COL_BT - 1) / SL_COL_BT), \
+                       dim3(CTile<N>::THREADS), 0, st, F, s.filt, T, s.W, s.R, c.b0, c.nb, c.p0,  \
+                       c.np, s.twH);                                                           \
     break;
     SL_FOR_EACH_N(X)
 #undef X
@@ -490,9 +566,9 @@ hipError_t launch_cols_fft_acc(const Sys2D &s, const float2 *U, float2 *ACC, Chu
   switch (s.H) {
 #define X(N)                                                                                    \
   case N:                                                                                       \
-    hipLaunchKernelGGL(k_cols_fft_acc<N>, row_grid<N>(s.W, c.nb), dim3(Tile<N>::THREADS), 0, st, \
-                       U, s.filt, s.psi, ACC, s.W, s.R, c.b0, c.p0, c.np, (int)first,           \
-                       (int)last, s.twH);                                                       \
+    hipLaunchKernelGGL(k_cols_fft_acc<N>, col_grid<N>(s.W, (c.nb + SL_COL_BT - 1) / SL_COL_BT),  \
+                       dim3(CTile<N>::THREADS), 0, st, U, s.filt, s.psi, ACC, s.W, s.R, c.b0,   \
+                       c.nb, c.p0, c.np, (int)first, (int)last, s.twH);                        \
     break;
     SL_FOR_EACH_N(X)
 #undef X

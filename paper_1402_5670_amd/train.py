@@ -33,17 +33,34 @@ from paper_1402_5670_amd import synthetic as syn      # noqa: E402
 PARAMS = B.CNN_PARAMS
 
 
-def init_params(J, C=32, seed=0):
-    """He-style initial weights per scale; the output bias starts at +2 so
-    that the initial gains are close to 1 (the identity shrinkage)."""
+def default_K(J):
+    """Per-scale threshold constants: 3 on every scale, 4 on the finest."""
+    return [3.0] * (J - 1) + [4.0]
+
+
+def init_params(J, C=32, seed=0, K=None, alpha=6.0, noise=0.1):
+    """Initial weights per scale that start as a smooth hard threshold.
+
+    Channel 0 carries the normalised magnitude x0 = |c| / (sigma ||psi||)
+    through the two hidden layers (centre taps 1, biases 0) and the output
+    is alpha * (x0 - K_j), so the initial gain sigmoid(alpha (x0 - K_j))
+    approximates thresholding at K_j sigma ||psi||.  All other weights are
+    He-initialised and scaled by noise, leaving room to learn context."""
     rng = np.random.default_rng(seed)
+    K = default_K(J) if K is None else list(K)
     out = np.zeros((J, PARAMS), dtype=np.float32)
     for j in range(J):
-        w1 = rng.standard_normal((C, 2, 3, 3)) * np.sqrt(2.0 / 18)
-        w2 = rng.standard_normal((C, C, 3, 3)) * np.sqrt(2.0 / (9 * C))
-        w3 = rng.standard_normal((1, C, 3, 3)) * np.sqrt(1.0 / (9 * C))
+        w1 = rng.standard_normal((C, 2, 3, 3)) * np.sqrt(2.0 / 18) * noise
+        w2 = rng.standard_normal((C, C, 3, 3)) * np.sqrt(2.0 / (9 * C)) * noise
+        w3 = rng.standard_normal((1, C, 3, 3)) * np.sqrt(1.0 / (9 * C)) * noise
+        w1[0] = 0.0
+        w1[0, 0, 1, 1] = 1.0
+        w2[0] = 0.0
+        w2[0, 0, 1, 1] = 1.0
+        w3[0, 0] = 0.0
+        w3[0, 0, 1, 1] = alpha
         blob = np.concatenate([w1.ravel(), np.zeros(C), w2.ravel(), np.zeros(C), w3.ravel(),
-                               [2.0]])
+                               [-alpha * K[j]]])
         out[j] = blob
     return out
 
@@ -54,9 +71,9 @@ def sigmas_for(seed, idx):
                      for i in idx], dtype=np.float32)
 
 
-def train(images=10000, batch=4, size=512, n_scales=4, shear_levels=(1, 1, 2, 2), lr=2e-3,
-          lr_min=1e-4, seed=0, init_seed=0, resume=None, out=None, log_every=50, device="cuda:0",
-          quiet=False):
+def train(images=10000, batch=4, size=512, n_scales=4, shear_levels=(1, 1, 2, 2), lr=1e-3,
+          lr_min=5e-5, seed=0, init_seed=0, resume=None, out=None, log_every=50, device="cuda:0",
+          quiet=False, K=None):
     import torch
     dev = torch.device(device)
     sysg = B.System((size, size), n_scales, shear_levels)
@@ -69,7 +86,7 @@ def train(images=10000, batch=4, size=512, n_scales=4, shear_levels=(1, 1, 2, 2)
         v = torch.from_numpy(ck["v"]).to(dev)
         start_step = int(ck["step"])
     else:
-        params = torch.from_numpy(init_params(J, seed=init_seed)).to(dev)
+        params = torch.from_numpy(init_params(J, seed=init_seed, K=K)).to(dev)
         m = torch.zeros_like(params)
         v = torch.zeros_like(params)
     net = B.Shrinkage(sysg, params)
@@ -177,7 +194,7 @@ def main():
     ap.add_argument("--images", type=int, default=10000)
     ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--size", type=int, default=512)
-    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--resume", default=None)
     ap.add_argument("--out", default="shrinkage_weights.npz")
