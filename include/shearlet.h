@@ -167,7 +167,7 @@ int sl_multi_run(sl_multi *m, int what, const float *const *x_dev, void *const *
                  float *const *scales_dev, const float *const *sigma_dev, const float *K_host,
                  float *const *out_dev, void *workspace_dev, size_t workspace_bytes,
                  void *stream);
-/* Times forward + inverse for each class at chunk sizes of 16..256 MiB that
+/* Times forward + inverse for each class at chunk sizes of 32..2048 MiB that
  * fit the class's current workspace slot and keeps the fastest (cached by
  * size, R, batch and storage type in the text file cache_path, if given).  */
 int sl_multi_autotune(sl_multi *m, const float *const *x_dev, void *const *coeffs_dev,

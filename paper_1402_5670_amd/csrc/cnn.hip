@@ -142,6 +142,162 @@ k_conv3x3(const uint16_t *__restrict__ in, const uint16_t *__restrict__ Wp,
 }
 
 // ---------------------------------------------------------------------------
+// fused inference: the three layers of one 16 x 32 output tile in LDS
+// ---------------------------------------------------------------------------
+// Regions (rows x cols): x0 22 x 38, h1 20 x 36, h2 18 x 34, output 16 x 32.
+// Activations outside the image are zero (the "same" zero padding of every
+// layer).  Layer 1 packs its 9 taps x 2 input channels into one K = 32 MFMA
+// operand (k = 2 t + c, k >= 18 zero); layers 2 and 3 are the per-tap
+// implicit GEMM of k_conv3x3.
+constexpr int FTH = 16, FTW = 32;
+constexpr int X0H = FTH + 6, X0W = FTW + 6;
+constexpr int H1H = FTH + 4, H1W = FTW + 4;
+constexpr int H2H = FTH + 2, H2W = FTW + 2;
+constexpr int kFusedThreads = 512;
+
+__global__ void __launch_bounds__(kFusedThreads)
+k_cnn_fused(const float *__restrict__ coef, CnnPlanes pl, int H, int W,
+            const uint16_t *__restrict__ W1k, const uint16_t *__restrict__ W2p,
+            const uint16_t *__restrict__ W3p, const float *__restrict__ params,
+            float *__restrict__ coef_out, float *__restrict__ gain) {
+  __shared__ __attribute__((aligned(16))) uint32_t x0s[X0H * X0W];
+  __shared__ __attribute__((aligned(16))) uint16_t h1s[H1H * H1W * CH];
+  __shared__ __attribute__((aligned(16))) uint16_t h2s[H2H * H2W * CH];
+  const int p = blockIdx.z;
+  const int ty0 = blockIdx.y * FTH, tx0 = blockIdx.x * FTW;
+  const size_t HWn = (size_t)H * W;
+  int b, i, j;
+  plane_info(pl, p, b, i, j);
+  const float *cpl = coef + ((size_t)b * pl.R + i) * HWn;
+  const float *P = params + (size_t)j * kCnnParams;
+  const float sg = pl.sigma[b];
+  const float v1 = sg * (255.0f / 50.0f);
+  for (int q = threadIdx.x; q < X0H * X0W; q += kFusedThreads) {
+    const int yy = ty0 - 3 + q / X0W, xx = tx0 - 3 + q % X0W;
+    uint32_t v = 0u;
+    if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
+      const float c = cpl[(size_t)yy * W + xx];
+      v = (uint32_t)f2bf(fabsf(c) / (sg * pl.l2[i])) | ((uint32_t)f2bf(v1) << 16);
+    }
+    x0s[q] = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NW = kFusedThreads / 64;
+  // ---- layer 1: 720 pixels = 45 blocks of 16
+  {
+    bf16x8 wb[2];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+      wb[nb] = *(const bf16x8 *)(W1k + (((size_t)j * 2 + nb) * 64 + lane) * 8);
+    for (int blk = wave; blk < (H1H * H1W) / 16; blk += NW) {
+      const int q = blk * 16 + (lane & 15);
+      const int r = q / H1W, c = q % H1W;
+      uint16_t av[8];
+#pragma unroll
+      for (int jj = 0; jj < 8; jj += 2) {
+        const int k = 8 * (lane >> 4) + jj;      // even: channel 0 of tap k / 2
+        const int t = k >> 1;
+        uint32_t w2 = 0u;
+        if (t < 9) w2 = x0s[(r + t / 3) * X0W + c + t % 3];
+        av[jj] = (uint16_t)(w2 & 0xFFFFu);
+        av[jj + 1] = (uint16_t)(w2 >> 16);
+      }
+      const bf16x8 a = *(const bf16x8 *)av;
+      f32x4 acc[2];
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wb[nb], f32x4{0.f, 0.f, 0.f, 0.f},
+                                                          0, 0, 0);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int q2 = blk * 16 + 4 * (lane >> 4) + e;
+        const int r2 = q2 / H1W, c2 = q2 % H1W;
+        const int yy = ty0 - 2 + r2, xx = tx0 - 2 + c2;
+        const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+          const int ch = 16 * nb + (lane & 15);
+          const float v = acc[nb][e] + P[kOffB1 + ch];
+          h1s[q2 * CH + ch] = (in && v > 0.f) ? f2bf(v) : (uint16_t)0;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // ---- layer 2: 612 pixels = 38.25 blocks of 16 (39, the last partial)
+  {
+    bf16x8 wb[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+        wb[t][nb] = *(const bf16x8 *)(W2p + ((((size_t)j * 9 + t) * 2 + nb) * 64 + lane) * 8);
+    constexpr int NPIX = H2H * H2W;
+    for (int blk = wave; blk < (NPIX + 15) / 16; blk += NW) {
+      int q = blk * 16 + (lane & 15);
+      if (q >= NPIX) q = NPIX - 1;                 // duplicate a valid pixel; not stored
+      const int r = q / H2W, c = q % H2W;
+      f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const int pix = (r + t / 3) * H1W + c + t % 3;
+        const bf16x8 a = *(const bf16x8 *)(h1s + pix * CH + 8 * (lane >> 4));
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wb[t][nb], acc[nb], 0, 0, 0);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int q2 = blk * 16 + 4 * (lane >> 4) + e;
+        if (q2 >= NPIX) continue;
+        const int r2 = q2 / H2W, c2 = q2 % H2W;
+        const int yy = ty0 - 1 + r2, xx = tx0 - 1 + c2;
+        const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+          const int ch = 16 * nb + (lane & 15);
+          const float v = acc[nb][e] + P[kOffB2 + ch];
+          h2s[q2 * CH + ch] = (in && v > 0.f) ? f2bf(v) : (uint16_t)0;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // ---- layer 3: 512 output pixels = 32 blocks of 16, channel 0 only
+  {
+    bf16x8 wb[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) wb[t] = *(const bf16x8 *)(W3p + (((size_t)j * 9 + t) * 64 + lane) * 8);
+    const float b3 = P[kOffB3];
+    for (int blk = wave; blk < (FTH * FTW) / 16; blk += NW) {
+      const int q = blk * 16 + (lane & 15);
+      const int r = q / FTW, c = q % FTW;
+      f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const int pix = (r + t / 3) * H2W + c + t % 3;
+        const bf16x8 a = *(const bf16x8 *)(h2s + pix * CH + 8 * (lane >> 4));
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wb[t], acc, 0, 0, 0);
+      }
+      if ((lane & 15) == 0) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int q2 = blk * 16 + 4 * (lane >> 4) + e;
+          const int yy = ty0 + q2 / FTW, xx = tx0 + q2 % FTW;
+          if (yy >= H || xx >= W) continue;
+          const float g = 1.0f / (1.0f + __expf(-(acc[e] + b3)));
+          const size_t co = (size_t)yy * W + xx;
+          const size_t full = ((size_t)b * pl.R + i) * HWn + co;
+          if (gain) gain[full] = g;
+          coef_out[full] = g * cpl[co];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // backward helpers
 // ---------------------------------------------------------------------------
 // dz = dL/dc' * c * g (1 - g) on channel 0 of a zero-padded bf16 tensor;
@@ -249,16 +405,20 @@ __global__ void k_reduce_partials(const float *__restrict__ partial, int nparts,
   outv[k] = s;
 }
 
-// Pack the conv B operands of every scale from the FP32 parameter blobs.
+// Pack the conv B operands of every scale from the FP32 parameter blobs,
+// layout [J][taps][NB][64 lanes][8]:
 // mode 0: forward layer (W[co][ci][t]); mode 1: transposed layer with flipped
-// taps (W'[ci][co][8 - t]) for the backward data pass.
+// taps (W'[ci][co][8 - t]) for the backward data pass; mode 2: layer 1 with
+// its 9 taps x 2 channels packed into one K = 32 operand (taps = 1).
 __global__ void k_pack(const float *__restrict__ params, int J, int layer, int mode,
                        uint16_t *__restrict__ Wp, int NB) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;   // over J*9*NB*64*8
-  const int total = J * 9 * NB * 64 * 8;
+  const int taps = mode == 2 ? 1 : 9;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;   // over J*taps*NB*64*8
+  const int total = J * taps * NB * 64 * 8;
   if (idx >= total) return;
-  const int jj = idx % 8, lane = (idx / 8) % 64, nb = (idx / 512) % NB, t = (idx / (512 * NB)) % 9;
-  const int js = idx / (512 * NB * 9);
+  const int jj = idx % 8, lane = (idx / 8) % 64, nb = (idx / 512) % NB;
+  const int t = (idx / (512 * NB)) % taps;
+  const int js = idx / (512 * NB * taps);
   const int n = 16 * nb + (lane & 15);          // output channel of this conv
   const int k = 8 * (lane >> 4) + jj;           // input channel of this conv
   const float *P = params + (size_t)js * kCnnParams;
@@ -267,7 +427,10 @@ __global__ void k_pack(const float *__restrict__ params, int J, int layer, int m
   const int off[3] = {kOffW1, kOffW2, kOffW3};
   const int cin[3] = {2, 32, 32}, cout[3] = {32, 32, 1};
   const int l = layer - 1;
-  if (mode == 0) {
+  if (mode == 2) {
+    const int tt = k >> 1, cc = k & 1;
+    if (n < 32 && tt < 9) v = P[off[0] + (n * 2 + cc) * 9 + tt];
+  } else if (mode == 0) {
     if (n < cout[l] && k < cin[l]) v = P[off[l] + (n * cin[l] + k) * 9 + t];
   } else {
     // transposed: this conv maps the layer's output channels (k) to its input channels (n)
@@ -316,6 +479,15 @@ hipError_t cnn_conv(const uint16_t *in, const uint16_t *Wp, int NB, const float 
                        bias_stride, pl, H, W, out, mask, coef, coef_out, gain);
   else
     return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t cnn_fused(const float *coef, const CnnPlanes &pl, int P, int H, int W,
+                     const uint16_t *W1k, const uint16_t *W2p, const uint16_t *W3p,
+                     const float *params, float *coef_out, float *gain, hipStream_t st) {
+  dim3 grid((W + FTW - 1) / FTW, (H + FTH - 1) / FTH, P);
+  hipLaunchKernelGGL(k_cnn_fused, grid, dim3(kFusedThreads), 0, st, coef, pl, H, W, W1k, W2p, W3p,
+                     params, coef_out, gain);
   return hipGetLastError();
 }
 
@@ -414,7 +586,8 @@ hipError_t cnn_grad_assemble(const float *dW1, const float *dW2, const float *dW
 
 hipError_t cnn_pack(const float *params, int J, int layer, int mode, uint16_t *Wp, int NB,
                     hipStream_t st) {
-  const int total = J * 9 * NB * 64 * 8;
+  // mode 2 (packed layer 1) has one operand per (scale, nb): index as taps = 1
+  const int total = J * (mode == 2 ? 1 : 9) * NB * 64 * 8;
   hipLaunchKernelGGL(k_pack, dim3((total + 255) / 256), dim3(256), 0, st, params, J, layer, mode,
                      Wp, NB);
   return hipGetLastError();

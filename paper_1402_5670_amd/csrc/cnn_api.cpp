@@ -22,6 +22,7 @@ using sl::kCnnParams;
 
 constexpr size_t kPackLayer2 = 9 * 2 * 512;   // u16 per scale, two output blocks
 constexpr size_t kPackLayer1 = 9 * 1 * 512;   // one output block
+constexpr size_t kPackK1 = 2 * 512;             // layer 1, taps packed into K
 constexpr int kWgradLen = 9 * 32 * 32 + 32;
 constexpr int kWgradBlocks = 512;
 constexpr int kErrBlocks = SL_SQERR_SCRATCH - 1;
@@ -29,7 +30,7 @@ constexpr int kErrBlocks = SL_SQERR_SCRATCH - 1;
 size_t al(size_t v) { return (v + 255) / 256 * 256; }
 
 struct Packed {
-  const uint16_t *w1, *w2, *w3, *w2t, *w3t;
+  const uint16_t *w1, *w2, *w3, *w2t, *w3t, *w1k;
 };
 
 Packed packed_view(const void *base, int J) {
@@ -40,6 +41,7 @@ Packed packed_view(const void *base, int J) {
   v.w3 = v.w2 + J * kPackLayer2;
   v.w2t = v.w3 + J * kPackLayer1;
   v.w3t = v.w2t + J * kPackLayer2;
+  v.w1k = v.w3t + J * kPackLayer2;
   return v;
 }
 
@@ -70,6 +72,13 @@ sl::CnnPlanes planes(const sl_system *s, int B, const float *sigma) {
 
 size_t act_bytes(const sl_system *s, int planes) {
   return al((size_t)planes * (size_t)s->cfg.npix() * 32 * 2);
+}
+
+// SL_CNN_LAYERWISE=1 selects the layer-by-layer inference (activations in
+// HBM) instead of the fused tile kernel; both compute the same network.
+bool layerwise() {
+  const char *e = std::getenv("SL_CNN_LAYERWISE");
+  return e && std::atoi(e) != 0;
 }
 
 int apply_chunk(const sl_system *s, int B) {
@@ -107,9 +116,9 @@ void plane_hw(const sl_system *s, int &H, int &W) {
 extern "C" {
 
 size_t sl_cnn_packed_bytes(int J) {
-  // w1, w2, w2t, w3t: two output blocks each; w3: one
+  // w1, w2, w2t, w3t: two output blocks each; w3: one; w1k: packed layer 1
   if (J < 1) return 0;
-  return (size_t)J * (4 * kPackLayer2 + kPackLayer1) * sizeof(uint16_t);
+  return (size_t)J * (4 * kPackLayer2 + kPackLayer1 + kPackK1) * sizeof(uint16_t);
 }
 
 int sl_cnn_pack(const float *params_dev, int J, void *packed_dev, void *stream) {
@@ -123,6 +132,7 @@ int sl_cnn_pack(const float *params_dev, int J, void *packed_dev, void *stream) 
   CK(sl::cnn_pack(params_dev, J, 3, 0, (uint16_t *)v.w3, 1, st));
   CK(sl::cnn_pack(params_dev, J, 2, 1, (uint16_t *)v.w2t, 2, st));
   CK(sl::cnn_pack(params_dev, J, 3, 1, (uint16_t *)v.w3t, 2, st));
+  CK(sl::cnn_pack(params_dev, J, 1, 2, (uint16_t *)v.w1k, 2, st));
   return SL_OK;
 }
 
@@ -130,7 +140,7 @@ int sl_cnn_workspace_size(const sl_system *s, int batch, int training, size_t *b
   if (!s || !bytes_out || batch < 1) return sl::set_error(SL_EINVAL, "bad arguments");
   const int P = batch * (s->R - 1);
   if (!training) {
-    *bytes_out = 2 * act_bytes(s, apply_chunk(s, batch));
+    *bytes_out = layerwise() ? 2 * act_bytes(s, apply_chunk(s, batch)) : 256;
   } else {
     const int J = s->cfg.J;
     *bytes_out = 5 * act_bytes(s, P) + al((size_t)batch * s->R * s->cfg.npix() * 4) +
@@ -156,6 +166,13 @@ int sl_cnn_apply(const sl_system *s, const float *params_dev, const void *packed
   plane_hw(s, H, W);
   const int J = s->cfg.J, P = batch * (s->R - 1), Pc = apply_chunk(s, batch);
   Packed pk = packed_view(packed_dev, J);
+  sl::CnnPlanes pl0 = planes(s, batch, sigma_dev);
+  if (!layerwise()) {
+    CK(sl::cnn_copy_lowpass(coeffs_dev, coeffs_out_dev, batch, s->R, (int)s->cfg.npix(), st));
+    CK(sl::cnn_fused(coeffs_dev, pl0, P, H, W, pk.w1k, pk.w2, pk.w3, params_dev, coeffs_out_dev,
+                     gains_dev, st));
+    return SL_OK;
+  }
   uint16_t *A = (uint16_t *)workspace_dev;
   uint16_t *Bf = (uint16_t *)((char *)workspace_dev + act_bytes(s, Pc));
   sl::CnnPlanes pl = planes(s, batch, sigma_dev);

@@ -155,17 +155,17 @@ k_cols_fft(const float2 *__restrict__ A, float2 *__restrict__ F, int W,
 }
 
 // Images per column block: the filter pair tile is loaded once and applied
-// to SL_COL_BT images (fewer filter re-reads, more registers).
-#ifndef SL_COL_BT
-#define SL_COL_BT 1
-#endif
+// to BT images (fewer filter re-reads, more registers).  Measured on MI355X
+// for 32 x 512^2: BT = 1 is best for the forward column pass, BT = 2 for the
+// inverse accumulation pass.
+constexpr int kFwdBT = 1, kInvBT = 2;
 
-template <int N>
+template <int N, int BT>
 __global__ void __launch_bounds__(CTile<N>::THREADS)
 k_cols_filter_ifft(const float2 *__restrict__ F, const float *__restrict__ filt,
                    float2 *__restrict__ T, int W, int R, int b0, int nb, int p0, int np,
                    const float2 *__restrict__ tw) {
-  constexpr int NT = CTile<N>::NT, M = CTile<N>::M, E = CTile<N>::E, BT = SL_COL_BT;
+  constexpr int NT = CTile<N>::NT, M = CTile<N>::M, E = CTile<N>::E;
   using PL = typename CTile<N>::PL;
   __shared__ float2 lds[M * N];
   const int m = threadIdx.x % M, t = threadIdx.x / M;
@@ -322,12 +322,12 @@ k_rows_coef_fft(const typename Store<DT>::T *__restrict__ coef, const float *__r
   }
 }
 
-template <int N>
+template <int N, int BT>
 __global__ void __launch_bounds__(CTile<N>::THREADS)
 k_cols_fft_acc(const float2 *__restrict__ U, const float *__restrict__ filt,
                const float *__restrict__ psi, float2 *__restrict__ ACC, int W, int R, int b0,
                int nb, int p0, int np, int first, int last, const float2 *__restrict__ tw) {
-  constexpr int NT = CTile<N>::NT, M = CTile<N>::M, E = CTile<N>::E, BT = SL_COL_BT;
+  constexpr int NT = CTile<N>::NT, M = CTile<N>::M, E = CTile<N>::E;
   using PL = typename CTile<N>::PL;
   __shared__ float2 lds[M * N];
   const int m = threadIdx.x % M, t = threadIdx.x / M;
@@ -478,7 +478,7 @@ hipError_t launch_cols_filter_ifft(const Sys2D &s, const float2 *F, float2 *T, C
   switch (s.H) {
 #define X(N)                                                                                 \
   case N:                                                                                    \
-    hipLaunchKernelGGL(k_cols_filter_ifft<N>, col_grid<N>(s.W, (c.nb + SL_COL_BT - 1) / SL_COL_BT), \
+    hipLaunchKernelGGL((k_cols_filter_ifft<N, kFwdBT>), col_grid<N>(s.W, (c.nb + kFwdBT - 1) / kFwdBT), \
                        dim3(CTile<N>::THREADS), 0, st, F, s.filt, T, s.W, s.R, c.b0, c.nb, c.p0,  \
                        c.np, s.twH);                                                           \
     break;
@@ -566,7 +566,7 @@ hipError_t launch_cols_fft_acc(const Sys2D &s, const float2 *U, float2 *ACC, Chu
   switch (s.H) {
 #define X(N)                                                                                    \
   case N:                                                                                       \
-    hipLaunchKernelGGL(k_cols_fft_acc<N>, col_grid<N>(s.W, (c.nb + SL_COL_BT - 1) / SL_COL_BT),  \
+    hipLaunchKernelGGL((k_cols_fft_acc<N, kInvBT>), col_grid<N>(s.W, (c.nb + kInvBT - 1) / kInvBT), \
                        dim3(CTile<N>::THREADS), 0, st, U, s.filt, s.psi, ACC, s.W, s.R, c.b0,   \
                        c.nb, c.p0, c.np, (int)first, (int)last, s.twH);                        \
     break;

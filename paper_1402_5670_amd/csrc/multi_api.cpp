@@ -170,7 +170,7 @@ int sl_multi_autotune(sl_multi *m, const float *const *x_dev, void *const *coeff
   if (!m || !workspace_dev) return sl::set_error(SL_EINVAL, "bad arguments");
   hipStream_t st = (hipStream_t)stream;
   auto cache = load_cache(cache_path);
-  static const size_t cand_mb[] = {16, 32, 64, 128, 256};
+  static const size_t cand_mb[] = {32, 128, 512, 2048};
   Bufs b{x_dev, coeffs_dev, scales_dev, nullptr, nullptr, out_dev, (char *)workspace_dev};
   hipEvent_t e0, e1;
   CK(hipEventCreate(&e0));

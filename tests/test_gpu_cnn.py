@@ -108,6 +108,21 @@ def test_cnn_forward_matches_oracle():
     assert np.sqrt(num / den) < 1e-3
 
 
+def test_fused_and_layerwise_inference_agree(monkeypatch):
+    # the fused tile kernel and the layer-by-layer path compute the same network;
+    # they differ only in the float32 summation order of layer 1
+    print("case: cnn fused vs layerwise 96x192 J=2 B=2", flush=True)
+    sysg, sig, c, params, pg = _setup(dims=(96, 192))
+    net = B.Shrinkage(sysg, pg)
+    g1 = torch.zeros_like(c)
+    net.apply(c, _gpu(sig), gains=g1)
+    monkeypatch.setenv("SL_CNN_LAYERWISE", "1")
+    g2 = torch.zeros_like(c)
+    net.apply(c, _gpu(sig), gains=g2)
+    torch.cuda.synchronize()
+    assert rel(g1[:, 1:].cpu().numpy(), g2[:, 1:].cpu().numpy()) < 1e-3
+
+
 def test_cnn_backward_matches_oracle():
     print("case: cnn backward 64x64 J=2 B=2", flush=True)
     sysg, sig, c, params, pg = _setup(seed=3)
