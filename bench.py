@@ -63,6 +63,27 @@ def pass_work(name, launches_chunks, H, W, R, B):
     return by, fl
 
 
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "transform2d_32x512_traffic.json")
+
+
+def measured_traffic(pass_name):
+    """HBM bytes per launch of the pass's kernel from the committed counter
+    summary (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None if
+    there is none or the kernel sources changed since it was taken."""
+    from paper_1402_5670_amd import profiling
+    if not os.path.exists(TRAFFIC_JSON):
+        return None
+    with open(TRAFFIC_JSON) as fh:
+        t = json.load(fh)
+    if t.get("source_hash") != profiling.source_hash():
+        return None
+    for k, v in t["kernels"].items():
+        if f"k_{pass_name}<" in k:
+            return {"read_bytes": v["read_bytes"], "write_bytes": v["write_bytes"],
+                    "bytes": v["read_bytes"] + v["write_bytes"], "kernel": k}
+    return None
+
+
 def cpu_baseline(seconds, sigmas, K, H, W, J, levels):
     """FP64 oracle (numpy FFT, one thread) on a bounded sample of images."""
     import numpy as np
@@ -172,7 +193,7 @@ def main():
         roof = {"bound": "alu", "achieved": round(d["TFLOPs"], 2),
                 "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(alu_frac, 4)}
     roof.update({"kernel": dom, "avg_launch_us": round(d["avg_launch_us"], 2),
-                 "launches_per_step": launches, "traffic": None})
+                 "launches_per_step": launches, "traffic": measured_traffic(dom)})
 
     step_bytes = sum(pass_work(n, 0, H, W, R, Bn)[0] for n in rep)
     psnr_noisy = float(np.mean([T.psnr(pairs[b][0], pairs[b][1]) for b in range(Bn)]))

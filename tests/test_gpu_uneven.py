@@ -96,3 +96,37 @@ def test_uneven_autotune(tmp_path):
     _check(systems, host, coeffs, scales, outs, 2e-3)
     # a second autotune reads the cache
     m.autotune(xs, coeffs, scales, outs, ws, cache_path=cache)
+
+
+def test_c4_uneven_64_images():
+    # 64 images, sizes drawn uniformly from {256, 384, 512, 1024}^2 (seed 4000), 3 scales
+    # [1, 1, 2] (R = 33), FP16 storage, autotuned and replayed from one graph; the oracle
+    # checks one image of every size class in full, the reconstruction every image
+    print("case: C4 uneven batch, 64 images", flush=True)
+    sizes = syn.uneven_sizes(64, 4000)
+    classes = sorted(set(sizes))
+    systems, xs, coeffs, scales, outs, host, seeds = [], [], [], [], [], [], []
+    for n in classes:
+        idx = [k for k, s in enumerate(sizes) if s == n]
+        imgs = np.stack([syn.noisy_cartoon2d(n, n, 4001 + k, 0.1)[1] for k in idx])
+        s = B.System((n, n), J, LEVELS, dtype="f16")
+        systems.append(s)
+        host.append(imgs)
+        xs.append(torch.from_numpy(imgs.astype(np.float32)).to(DEV))
+        c, sc = s.alloc_coeffs(len(idx), DEV)
+        coeffs.append(c)
+        scales.append(sc)
+        outs.append(torch.empty((len(idx), n, n), device=DEV))
+    m = B.Multi(systems, [h.shape[0] for h in host])
+    ws = torch.empty(m.workspace_bytes(), dtype=torch.uint8, device=DEV)
+    m.autotune(xs, coeffs, scales, outs, ws)
+    m.graph_build(3, xs, coeffs, scales, outs=outs, workspace=ws)
+    m.graph_launch()
+    torch.cuda.synchronize()
+    for s, imgs, c, sc, o in zip(systems, host, coeffs, scales, outs):
+        assert rel(o.cpu().numpy(), imgs) < 2e-3
+        orc = S.build_2d(s.dims, J, LEVELS)
+        cd = c[0].float().cpu().numpy().astype(np.float64) * sc[0].cpu().numpy()[:, None, None]
+        err = rel(cd, T.forward(imgs[0], orc.filters))
+        print(f"size {s.dims[0]}: {imgs.shape[0]} images, coefficient relL2 {err:.2e}", flush=True)
+        assert err < 2e-3
