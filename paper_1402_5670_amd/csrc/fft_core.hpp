@@ -142,7 +142,27 @@ struct LdsLine {
 template <int N>
 constexpr int row_lds_len() { return N + N / 8; }
 
-template <class PL, int S_, bool INV>
+// Exchanges between radix stages need every thread of a line to have written
+// its values before any thread reads.  When all threads of a line sit in one
+// wavefront (row tiles with NT dividing 64), the wavefront's LDS operations
+// execute in issue order and a code-motion fence suffices: waves of a block
+// then run their lines independently.  Otherwise the block synchronises.
+template <bool WAVE>
+__device__ __forceinline__ void line_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// Lines of NT threads lie inside one wavefront when NT divides 64.
+template <int NT>
+constexpr bool wave_lines() { return NT <= 64 && 64 % NT == 0; }
+
+template <class PL, int S_, bool INV, bool WAVE = false>
 __device__ __forceinline__ void fft_stage(float2 (&v)[PL::E], int t, const LdsLine &lds,
                                           const float2 *__restrict__ tw) {
   constexpr int N = PL::N;
@@ -158,7 +178,7 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[PL::E], int t, const LdsLi
 #pragma unroll
       for (int q = 0; q < r; ++q) x[b][q] = v[b + q * NB];
   } else {
-    __syncthreads();
+    line_sync<WAVE>();
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       int i = t + b * NT;
@@ -185,7 +205,7 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[PL::E], int t, const LdsLi
 #pragma unroll
       for (int q = 0; q < r; ++q) v[b + q * NB] = x[b][q];
   } else {
-    if constexpr (S_ > 0) __syncthreads();
+    if constexpr (S_ > 0) line_sync<WAVE>();
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       int i = t + b * NT;
@@ -197,29 +217,31 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[PL::E], int t, const LdsLi
   }
 }
 
-template <class PL, bool INV, int S_ = 0>
+template <class PL, bool INV, bool WAVE, int S_ = 0>
 __device__ __forceinline__ void fft_stages(float2 (&v)[PL::E], int t, const LdsLine &lds,
                                            const float2 *__restrict__ tw) {
   if constexpr (S_ < PL::S) {
-    fft_stage<PL, S_, INV>(v, t, lds, tw);
-    fft_stages<PL, INV, S_ + 1>(v, t, lds, tw);
+    fft_stage<PL, S_, INV, WAVE>(v, t, lds, tw);
+    fft_stages<PL, INV, WAVE, S_ + 1>(v, t, lds, tw);
   }
 }
 
 // Full length-N FFT of one line held in registers (see file comment).  The
 // leading barrier makes it safe to call repeatedly on the same LDS buffer.
 // A single-stage plan never touches LDS.
-template <class PL, bool INV>
+template <class PL, bool INV, bool WAVE = false>
 __device__ __forceinline__ void fft_line_p(float2 (&v)[PL::E], int t, const LdsLine &lds,
                                            const float2 *__restrict__ tw) {
-  if constexpr (PL::S > 1) __syncthreads();
-  fft_stages<PL, INV>(v, t, lds, tw);
+  if constexpr (PL::S > 1) line_sync<WAVE>();
+  fft_stages<PL, INV, WAVE>(v, t, lds, tw);
 }
 
+// Row lines (one line per NT consecutive threads): wavefront-local exchanges
+// whenever the line fits in a wavefront.
 template <int N, bool INV>
 __device__ __forceinline__ void fft_line(float2 (&v)[Plan<N>::E], int t, const LdsLine &lds,
                                          const float2 *__restrict__ tw) {
-  fft_line_p<Plan<N>, INV>(v, t, lds, tw);
+  fft_line_p<Plan<N>, INV, wave_lines<Plan<N>::NT>()>(v, t, lds, tw);
 }
 
 }  // namespace sl

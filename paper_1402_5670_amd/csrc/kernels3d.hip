@@ -65,7 +65,7 @@ k_z_filter_ifft(const float2 *__restrict__ F, const Sub3D *__restrict__ subs,
       const float bb = ib < R ? filter3d(db, tab, z, y, x) : 0.f;
       v[e] = make_float2(f[e].x * a - f[e].y * bb, f[e].y * a + f[e].x * bb);
     }
-    fft_line<N, true>(v, t, LdsLine{lds + m, M}, tw);
+    fft_line_p<Plan<N>, true>(v, t, LdsLine{lds + m, M}, tw);
     if (ok) {
       float2 *To = T + ((size_t)blockIdx.y * np + pp) * vol + col;
 #pragma unroll
@@ -104,7 +104,7 @@ k_z_fft_acc(const float2 *__restrict__ U, const Sub3D *__restrict__ subs,
     float2 v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = Ui[(size_t)(t + e * NT) * HW];
-    fft_line<N, false>(v, t, LdsLine{lds + m, M}, tw);
+    fft_line_p<Plan<N>, false>(v, t, LdsLine{lds + m, M}, tw);
     const Sub3D da = subs[ia];
     const Sub3D db = subs[ib < R ? ib : ia];
 #pragma unroll
@@ -123,7 +123,7 @@ k_z_fft_acc(const float2 *__restrict__ U, const Sub3D *__restrict__ subs,
       const float d = ps[(size_t)(t + e * NT) * HW];
       acc[e] = make_float2(acc[e].x / d, acc[e].y / d);
     }
-    fft_line<N, true>(acc, t, LdsLine{lds + m, M}, tw);
+    fft_line_p<Plan<N>, true>(acc, t, LdsLine{lds + m, M}, tw);
   }
   if (ok) {
 #pragma unroll
