@@ -334,6 +334,10 @@ int sl_build_system(const sl_config *cfg, sl_system **out) {
     delete s;
     return fail(SL_EHIP, "no HIP device");
   }
+  if (hipDeviceGetAttribute(&s->num_cu, hipDeviceAttributeMultiprocessorCount, s->device) !=
+          hipSuccess ||
+      s->num_cu < 1)
+    s->num_cu = 1;
   const char *cap_env = std::getenv("SL_CHUNK_MB");
   // default 2 GiB: on MI355X larger chunks (fewer launches, no repeated
   // accumulator round trips) measured faster than Infinity-Cache-sized ones

@@ -142,158 +142,243 @@ k_conv3x3(const uint16_t *__restrict__ in, const uint16_t *__restrict__ Wp,
 }
 
 // ---------------------------------------------------------------------------
-// fused inference: the three layers of one 16 x 32 output tile in LDS
+// fused inference: the three layers of 16 x 32 output tiles in LDS
 // ---------------------------------------------------------------------------
 // Regions (rows x cols): x0 22 x 38, h1 20 x 36, h2 18 x 34, output 16 x 32.
 // Activations outside the image are zero (the "same" zero padding of every
-// layer).  Layer 1 packs its 9 taps x 2 input channels into one K = 32 MFMA
-// operand (k = 2 t + c, k >= 18 zero); layers 2 and 3 are the per-tap
-// implicit GEMM of k_conv3x3.
+// layer).  The weights are the A operand and the activations the B operand,
+// so each lane receives 4 consecutive output channels of one pixel
+// (D[m = channel][n = pixel]) and stores them with one 8-byte LDS write.
+// Layer 1 packs its 9 taps x 2 input channels into one K = 32 operand
+// (k = 2 t + c, k >= 18 zero); layer 2 is the per-tap implicit GEMM.  Layer 3
+// has one output channel: an MFMA with the 9 taps on the M axis yields
+// D[t][p] = sum_ci W3[ci][t] h2[p][ci] for every h2 pixel p, and the output is
+// b3 + sum_t D[t][p + offset(t)].
+// h1 and h2 pixels are padded to 40 channels (80 bytes), which spreads the
+// 16 pixels of an operand read over distinct LDS banks.
 constexpr int FTH = 16, FTW = 32;
 constexpr int X0H = FTH + 6, X0W = FTW + 6;
 constexpr int H1H = FTH + 4, H1W = FTW + 4;
 constexpr int H2H = FTH + 2, H2W = FTW + 2;
+constexpr int NX0 = X0H * X0W, NH1 = H1H * H1W, NH2 = H2H * H2W;
+constexpr int CHP = 40;
 constexpr int kFusedThreads = 512;
+constexpr int kX0PerThread = (NX0 + kFusedThreads - 1) / kFusedThreads;
+// LDS (bytes): h1 | h2 (x0 shares it) | 2 x raw centre coefficients.  The
+// layer-3 partial sums D[9][NH2] reuse the h1 region once layer 2 is done.
+constexpr int kLdsH1 = NH1 * CHP * 2, kLdsH2 = NH2 * CHP * 2, kLdsC = FTH * FTW * 4;
+static_assert(NX0 * 4 <= kLdsH2, "x0 must fit in the h2 region");
+static_assert(9 * NH2 * 4 <= kLdsH1, "layer-3 partial sums must fit in the h1 region");
+
+struct FusedTile {
+  int p, ty0, tx0, b, i, j;
+};
+
+__device__ __forceinline__ FusedTile fused_tile(const CnnPlanes &pl, int tile, int tiles_x,
+                                                int tiles_per_plane) {
+  FusedTile f;
+  f.p = tile / tiles_per_plane;
+  const int r = tile % tiles_per_plane;
+  f.ty0 = (r / tiles_x) * FTH;
+  f.tx0 = (r % tiles_x) * FTW;
+  plane_info(pl, f.p, f.b, f.i, f.j);
+  return f;
+}
 
 __global__ void __launch_bounds__(kFusedThreads)
-k_cnn_fused(const float *__restrict__ coef, CnnPlanes pl, int H, int W,
+k_cnn_fused(const float *__restrict__ coef, CnnPlanes pl, int H, int W, int ntiles,
             const uint16_t *__restrict__ W1k, const uint16_t *__restrict__ W2p,
-            const uint16_t *__restrict__ W3p, const float *__restrict__ params,
+            const uint16_t *__restrict__ W3m, const float *__restrict__ params,
             float *__restrict__ coef_out, float *__restrict__ gain) {
-  __shared__ __attribute__((aligned(16))) uint32_t x0s[X0H * X0W];
-  __shared__ __attribute__((aligned(16))) uint16_t h1s[H1H * H1W * CH];
-  __shared__ __attribute__((aligned(16))) uint16_t h2s[H2H * H2W * CH];
-  const int p = blockIdx.z;
-  const int ty0 = blockIdx.y * FTH, tx0 = blockIdx.x * FTW;
-  const size_t HWn = (size_t)H * W;
-  int b, i, j;
-  plane_info(pl, p, b, i, j);
-  const float *cpl = coef + ((size_t)b * pl.R + i) * HWn;
-  const float *P = params + (size_t)j * kCnnParams;
-  const float sg = pl.sigma[b];
-  const float v1 = sg * (255.0f / 50.0f);
-  for (int q = threadIdx.x; q < X0H * X0W; q += kFusedThreads) {
-    const int yy = ty0 - 3 + q / X0W, xx = tx0 - 3 + q % X0W;
-    uint32_t v = 0u;
-    if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
-      const float c = cpl[(size_t)yy * W + xx];
-      v = (uint32_t)f2bf(fabsf(c) / (sg * pl.l2[i])) | ((uint32_t)f2bf(v1) << 16);
-    }
-    x0s[q] = v;
-  }
-  __syncthreads();
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kLdsH1 + kLdsH2 + 2 * kLdsC];
+  uint16_t *h1s = (uint16_t *)smem;
+  float *d3 = (float *)smem;                         // layer-3 partials, after layer 2
+  uint16_t *h2s = (uint16_t *)(smem + kLdsH1);
+  uint32_t *x0s = (uint32_t *)(smem + kLdsH1);       // before layer 2
+  float *cs = (float *)(smem + kLdsH1 + kLdsH2);     // [2][FTH * FTW]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   constexpr int NW = kFusedThreads / 64;
-  // ---- layer 1: 720 pixels = 45 blocks of 16
-  {
-    bf16x8 wb[2];
+  const int tiles_x = (W + FTW - 1) / FTW;
+  const int tiles_per_plane = tiles_x * ((H + FTH - 1) / FTH);
+  const size_t HWn = (size_t)H * W;
+
+  // stage the x0 region of a tile: registers hold raw coefficients (0 outside)
+  float xr[kX0PerThread];
+  auto fetch = [&](const FusedTile &f) {
+    const float *cpl = coef + ((size_t)f.b * pl.R + f.i) * HWn;
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb)
-      wb[nb] = *(const bf16x8 *)(W1k + (((size_t)j * 2 + nb) * 64 + lane) * 8);
-    for (int blk = wave; blk < (H1H * H1W) / 16; blk += NW) {
+    for (int u = 0; u < kX0PerThread; ++u) {
+      const int q = threadIdx.x + u * kFusedThreads;
+      const int yy = f.ty0 - 3 + q / X0W, xx = f.tx0 - 3 + q % X0W;
+      xr[u] = (q < NX0 && yy >= 0 && yy < H && xx >= 0 && xx < W) ? cpl[(size_t)yy * W + xx] : 0.f;
+    }
+  };
+  auto stage = [&](const FusedTile &f, int buf) {
+    const float sg = pl.sigma[f.b];
+    const float inv = 1.0f / (sg * pl.l2[f.i]);
+    const uint32_t ch1 = (uint32_t)f2bf(sg * (255.0f / 50.0f)) << 16;
+#pragma unroll
+    for (int u = 0; u < kX0PerThread; ++u) {
+      const int q = threadIdx.x + u * kFusedThreads;
+      if (q >= NX0) continue;
+      const int r = q / X0W, c = q % X0W;
+      const int yy = f.ty0 - 3 + r, xx = f.tx0 - 3 + c;
+      const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
+      x0s[q] = in ? ((uint32_t)f2bf(fabsf(xr[u]) * inv) | ch1) : 0u;
+      if (r >= 3 && r < 3 + FTH && c >= 3 && c < 3 + FTW) cs[buf * FTH * FTW + (r - 3) * FTW + c - 3] = xr[u];
+    }
+  };
+
+  // weights of the current scale (reloaded when the scale changes)
+  bf16x8 w1[2], w2[9][2], w3;
+  float bias1[2][4], bias2[2][4], b3 = 0.f;
+  int cur_j = -1;
+  auto load_weights = [&](int j) {
+    const float *P = params + (size_t)j * kCnnParams;
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+      w1[nb] = *(const bf16x8 *)(W1k + (((size_t)j * 2 + nb) * 64 + lane) * 8);
+#pragma unroll
+      for (int t = 0; t < 9; ++t)
+        w2[t][nb] = *(const bf16x8 *)(W2p + ((((size_t)j * 9 + t) * 2 + nb) * 64 + lane) * 8);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ch = 16 * nb + 4 * (lane >> 4) + q;
+        bias1[nb][q] = P[kOffB1 + ch];
+        bias2[nb][q] = P[kOffB2 + ch];
+      }
+    }
+    w3 = *(const bf16x8 *)(W3m + ((size_t)j * 64 + lane) * 8);
+    b3 = P[kOffB3];
+  };
+
+  int tile = blockIdx.x;
+  if (tile >= ntiles) return;
+  FusedTile f = fused_tile(pl, tile, tiles_x, tiles_per_plane);
+  fetch(f);
+  stage(f, 0);
+  int buf = 0;
+  __syncthreads();
+  for (;;) {
+    if (f.j != cur_j) {
+      load_weights(f.j);
+      cur_j = f.j;
+    }
+    // ---- layer 1: NH1 = 720 pixels, 45 blocks of 16
+    for (int blk = wave; blk < NH1 / 16; blk += NW) {
       const int q = blk * 16 + (lane & 15);
       const int r = q / H1W, c = q % H1W;
       uint16_t av[8];
 #pragma unroll
       for (int jj = 0; jj < 8; jj += 2) {
-        const int k = 8 * (lane >> 4) + jj;      // even: channel 0 of tap k / 2
-        const int t = k >> 1;
-        uint32_t w2 = 0u;
-        if (t < 9) w2 = x0s[(r + t / 3) * X0W + c + t % 3];
-        av[jj] = (uint16_t)(w2 & 0xFFFFu);
-        av[jj + 1] = (uint16_t)(w2 >> 16);
+        const int t = 4 * (lane >> 4) + (jj >> 1);   // k = 8 (lane / 16) + jj = 2 t + channel
+        uint32_t v = 0u;
+        if (t < 9) v = x0s[(r + t / 3) * X0W + c + t % 3];
+        av[jj] = (uint16_t)(v & 0xFFFFu);
+        av[jj + 1] = (uint16_t)(v >> 16);
       }
-      const bf16x8 a = *(const bf16x8 *)av;
-      f32x4 acc[2];
+      const bf16x8 xb = *(const bf16x8 *)av;
+      const int yy = f.ty0 - 2 + r, xx = f.tx0 - 2 + c;
+      const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
 #pragma unroll
-      for (int nb = 0; nb < 2; ++nb)
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wb[nb], f32x4{0.f, 0.f, 0.f, 0.f},
-                                                          0, 0, 0);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int q2 = blk * 16 + 4 * (lane >> 4) + e;
-        const int r2 = q2 / H1W, c2 = q2 % H1W;
-        const int yy = ty0 - 2 + r2, xx = tx0 - 2 + c2;
-        const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
-          const int ch = 16 * nb + (lane & 15);
-          const float v = acc[nb][e] + P[kOffB1 + ch];
-          h1s[q2 * CH + ch] = (in && v > 0.f) ? f2bf(v) : (uint16_t)0;
-        }
-      }
-    }
-  }
-  __syncthreads();
-  // ---- layer 2: 612 pixels = 38.25 blocks of 16 (39, the last partial)
-  {
-    bf16x8 wb[9][2];
-#pragma unroll
-    for (int t = 0; t < 9; ++t)
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb)
-        wb[t][nb] = *(const bf16x8 *)(W2p + ((((size_t)j * 9 + t) * 2 + nb) * 64 + lane) * 8);
-    constexpr int NPIX = H2H * H2W;
-    for (int blk = wave; blk < (NPIX + 15) / 16; blk += NW) {
-      int q = blk * 16 + (lane & 15);
-      if (q >= NPIX) q = NPIX - 1;                 // duplicate a valid pixel; not stored
-      const int r = q / H2W, c = q % H2W;
-      f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
-#pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        const int pix = (r + t / 3) * H1W + c + t % 3;
-        const bf16x8 a = *(const bf16x8 *)(h1s + pix * CH + 8 * (lane >> 4));
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
-          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wb[t][nb], acc[nb], 0, 0, 0);
-      }
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int q2 = blk * 16 + 4 * (lane >> 4) + e;
-        if (q2 >= NPIX) continue;
-        const int r2 = q2 / H2W, c2 = q2 % H2W;
-        const int yy = ty0 - 1 + r2, xx = tx0 - 1 + c2;
-        const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
-          const int ch = 16 * nb + (lane & 15);
-          const float v = acc[nb][e] + P[kOffB2 + ch];
-          h2s[q2 * CH + ch] = (in && v > 0.f) ? f2bf(v) : (uint16_t)0;
-        }
-      }
-    }
-  }
-  __syncthreads();
-  // ---- layer 3: 512 output pixels = 32 blocks of 16, channel 0 only
-  {
-    bf16x8 wb[9];
-#pragma unroll
-    for (int t = 0; t < 9; ++t) wb[t] = *(const bf16x8 *)(W3p + (((size_t)j * 9 + t) * 64 + lane) * 8);
-    const float b3 = P[kOffB3];
-    for (int blk = wave; blk < (FTH * FTW) / 16; blk += NW) {
-      const int q = blk * 16 + (lane & 15);
-      const int r = q / FTW, c = q % FTW;
-      f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        const int pix = (r + t / 3) * H2W + c + t % 3;
-        const bf16x8 a = *(const bf16x8 *)(h2s + pix * CH + 8 * (lane >> 4));
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wb[t], acc, 0, 0, 0);
-      }
-      if ((lane & 15) == 0) {
+      for (int nb = 0; nb < 2; ++nb) {
+        const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[nb], xb, f32x4{0.f, 0.f, 0.f, 0.f},
+                                                                0, 0, 0);
+        uint16_t o[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int q2 = blk * 16 + 4 * (lane >> 4) + e;
-          const int yy = ty0 + q2 / FTW, xx = tx0 + q2 % FTW;
-          if (yy >= H || xx >= W) continue;
-          const float g = 1.0f / (1.0f + __expf(-(acc[e] + b3)));
-          const size_t co = (size_t)yy * W + xx;
-          const size_t full = ((size_t)b * pl.R + i) * HWn + co;
-          if (gain) gain[full] = g;
-          coef_out[full] = g * cpl[co];
+          const float v = d[e] + bias1[nb][e];
+          o[e] = (in && v > 0.f) ? f2bf(v) : (uint16_t)0;
+        }
+        *(uint2 *)(h1s + q * CHP + 16 * nb + 4 * (lane >> 4)) = *(const uint2 *)o;
+      }
+    }
+    __syncthreads();
+    // prefetch the next tile's coefficients; they land during layers 2 and 3
+    const int next = tile + gridDim.x;
+    FusedTile fn = f;
+    if (next < ntiles) {
+      fn = fused_tile(pl, next, tiles_x, tiles_per_plane);
+      fetch(fn);
+    }
+    // ---- layer 2: NH2 = 612 pixels, 39 blocks of 16 (the last has 4), two per step
+    for (int b0 = 2 * wave; b0 < (NH2 + 15) / 16; b0 += 2 * NW) {
+      f32x4 acc[2][2];
+      int qq[2];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        int q = (b0 + s) * 16 + (lane & 15);
+        qq[s] = q;
+        if (q >= NH2) q = NH2 - 1;       // duplicate a valid pixel; not stored
+        const int r = q / H2W, c = q % H2W;
+        acc[s][0] = f32x4{0.f, 0.f, 0.f, 0.f};
+        acc[s][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+          const int pix = (r + t / 3) * H1W + c + t % 3;
+          const bf16x8 xb = *(const bf16x8 *)(h1s + pix * CHP + 8 * (lane >> 4));
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb)
+            acc[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[t][nb], xb, acc[s][nb], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int q = qq[s];
+        if (q >= NH2) continue;
+        const int r = q / H2W, c = q % H2W;
+        const int yy = f.ty0 - 1 + r, xx = f.tx0 - 1 + c;
+        const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+          uint16_t o[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float v = acc[s][nb][e] + bias2[nb][e];
+            o[e] = (in && v > 0.f) ? f2bf(v) : (uint16_t)0;
+          }
+          *(uint2 *)(h2s + q * CHP + 16 * nb + 4 * (lane >> 4)) = *(const uint2 *)o;
         }
       }
     }
+    __syncthreads();
+    // ---- layer 3, per-tap partial sums over the 32 channels of every h2 pixel
+    for (int blk = wave; blk < (NH2 + 15) / 16; blk += NW) {
+      const int q = blk * 16 + (lane & 15);
+      const int qc = q < NH2 ? q : NH2 - 1;
+      const bf16x8 xb = *(const bf16x8 *)(h2s + qc * CHP + 8 * (lane >> 4));
+      const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3, xb, f32x4{0.f, 0.f, 0.f, 0.f},
+                                                              0, 0, 0);
+      if (q < NH2) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int t = 4 * (lane >> 4) + e;
+          if (t < 9) d3[t * NH2 + q] = d[e];
+        }
+      }
+    }
+    __syncthreads();
+    // ---- output: one pixel per thread
+    {
+      const int r = threadIdx.x / FTW, c = threadIdx.x % FTW;
+      float z = b3;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) z += d3[t * NH2 + (r + t / 3) * H2W + c + t % 3];
+      const int yy = f.ty0 + r, xx = f.tx0 + c;
+      if (yy < H && xx < W) {
+        const float g = 1.0f / (1.0f + __expf(-z));
+        const size_t co = ((size_t)f.b * pl.R + f.i) * HWn + (size_t)yy * W + xx;
+        if (gain) gain[co] = g;
+        coef_out[co] = g * cs[buf * FTH * FTW + threadIdx.x];
+      }
+    }
+    if (next >= ntiles) break;
+    // h2 reads ended at the barrier above: stage the next tile into x0 / cs
+    buf ^= 1;
+    stage(fn, buf);
+    tile = next;
+    f = fn;
+    __syncthreads();
   }
 }
 
@@ -412,7 +497,7 @@ __global__ void k_reduce_partials(const float *__restrict__ partial, int nparts,
 // its 9 taps x 2 channels packed into one K = 32 operand (taps = 1).
 __global__ void k_pack(const float *__restrict__ params, int J, int layer, int mode,
                        uint16_t *__restrict__ Wp, int NB) {
-  const int taps = mode == 2 ? 1 : 9;
+  const int taps = mode >= 2 ? 1 : 9;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;   // over J*taps*NB*64*8
   const int total = J * taps * NB * 64 * 8;
   if (idx >= total) return;
@@ -430,6 +515,9 @@ __global__ void k_pack(const float *__restrict__ params, int J, int layer, int m
   if (mode == 2) {
     const int tt = k >> 1, cc = k & 1;
     if (n < 32 && tt < 9) v = P[off[0] + (n * 2 + cc) * 9 + tt];
+  } else if (mode == 3) {
+    // layer 3 with the taps as output rows: row n = tap, column k = channel
+    if (n < 9) v = P[off[2] + k * 9 + n];
   } else if (mode == 0) {
     if (n < cout[l] && k < cin[l]) v = P[off[l] + (n * cin[l] + k) * 9 + t];
   } else {
@@ -483,11 +571,14 @@ hipError_t cnn_conv(const uint16_t *in, const uint16_t *Wp, int NB, const float 
 }
 
 hipError_t cnn_fused(const float *coef, const CnnPlanes &pl, int P, int H, int W,
-                     const uint16_t *W1k, const uint16_t *W2p, const uint16_t *W3p,
-                     const float *params, float *coef_out, float *gain, hipStream_t st) {
-  dim3 grid((W + FTW - 1) / FTW, (H + FTH - 1) / FTH, P);
-  hipLaunchKernelGGL(k_cnn_fused, grid, dim3(kFusedThreads), 0, st, coef, pl, H, W, W1k, W2p, W3p,
-                     params, coef_out, gain);
+                     const uint16_t *W1k, const uint16_t *W2p, const uint16_t *W3m,
+                     const float *params, float *coef_out, float *gain, int nblocks,
+                     hipStream_t st) {
+  const int ntiles = P * ((W + FTW - 1) / FTW) * ((H + FTH - 1) / FTH);
+  const int grid = nblocks < ntiles ? nblocks : ntiles;
+  if (grid < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_cnn_fused, dim3(grid), dim3(kFusedThreads), 0, st, coef, pl, H, W, ntiles,
+                     W1k, W2p, W3m, params, coef_out, gain);
   return hipGetLastError();
 }
 

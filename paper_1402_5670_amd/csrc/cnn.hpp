@@ -44,9 +44,12 @@ hipError_t cnn_conv(const uint16_t *in, const uint16_t *Wp, int NB, const float 
                     int bias_stride, const CnnPlanes &pl, int P, int H, int W, int mode,
                     uint16_t *out, const uint16_t *mask, const float *coef, float *coef_out,
                     float *gain, hipStream_t st);
+// fused inference over P planes; a persistent grid of nblocks blocks (one
+// per compute unit: the kernel needs 107 KiB of LDS) walks the 16 x 32 tiles
 hipError_t cnn_fused(const float *coef, const CnnPlanes &pl, int P, int H, int W,
-                     const uint16_t *W1k, const uint16_t *W2p, const uint16_t *W3p,
-                     const float *params, float *coef_out, float *gain, hipStream_t st);
+                     const uint16_t *W1k, const uint16_t *W2p, const uint16_t *W3m,
+                     const float *params, float *coef_out, float *gain, int nblocks,
+                     hipStream_t st);
 hipError_t cnn_dz(const float *dcoef, const float *coef, const float *gain, const CnnPlanes &pl,
                   int P, int H, int W, uint16_t *dz, float *dzf, hipStream_t st);
 // weight gradient over planes [plane0, plane0 + nplanes) (local indices)

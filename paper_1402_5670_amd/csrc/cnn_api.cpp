@@ -23,6 +23,7 @@ using sl::kCnnParams;
 constexpr size_t kPackLayer2 = 9 * 2 * 512;   // u16 per scale, two output blocks
 constexpr size_t kPackLayer1 = 9 * 1 * 512;   // one output block
 constexpr size_t kPackK1 = 2 * 512;             // layer 1, taps packed into K
+constexpr size_t kPackTaps3 = 512;              // layer 3, taps on the M axis
 constexpr int kWgradLen = 9 * 32 * 32 + 32;
 constexpr int kWgradBlocks = 512;
 constexpr int kErrBlocks = SL_SQERR_SCRATCH - 1;
@@ -30,7 +31,7 @@ constexpr int kErrBlocks = SL_SQERR_SCRATCH - 1;
 size_t al(size_t v) { return (v + 255) / 256 * 256; }
 
 struct Packed {
-  const uint16_t *w1, *w2, *w3, *w2t, *w3t, *w1k;
+  const uint16_t *w1, *w2, *w3, *w2t, *w3t, *w1k, *w3m;
 };
 
 Packed packed_view(const void *base, int J) {
@@ -42,6 +43,7 @@ Packed packed_view(const void *base, int J) {
   v.w2t = v.w3 + J * kPackLayer1;
   v.w3t = v.w2t + J * kPackLayer2;
   v.w1k = v.w3t + J * kPackLayer2;
+  v.w3m = v.w1k + J * kPackK1;
   return v;
 }
 
@@ -116,9 +118,10 @@ void plane_hw(const sl_system *s, int &H, int &W) {
 extern "C" {
 
 size_t sl_cnn_packed_bytes(int J) {
-  // w1, w2, w2t, w3t: two output blocks each; w3: one; w1k: packed layer 1
+  // w1, w2, w2t, w3t: two output blocks each; w3: one; w1k: packed layer 1;
+  // w3m: layer 3 with the taps as output rows
   if (J < 1) return 0;
-  return (size_t)J * (4 * kPackLayer2 + kPackLayer1 + kPackK1) * sizeof(uint16_t);
+  return (size_t)J * (4 * kPackLayer2 + kPackLayer1 + kPackK1 + kPackTaps3) * sizeof(uint16_t);
 }
 
 int sl_cnn_pack(const float *params_dev, int J, void *packed_dev, void *stream) {
@@ -133,6 +136,7 @@ int sl_cnn_pack(const float *params_dev, int J, void *packed_dev, void *stream) 
   CK(sl::cnn_pack(params_dev, J, 2, 1, (uint16_t *)v.w2t, 2, st));
   CK(sl::cnn_pack(params_dev, J, 3, 1, (uint16_t *)v.w3t, 2, st));
   CK(sl::cnn_pack(params_dev, J, 1, 2, (uint16_t *)v.w1k, 2, st));
+  CK(sl::cnn_pack(params_dev, J, 3, 3, (uint16_t *)v.w3m, 1, st));
   return SL_OK;
 }
 
@@ -169,8 +173,8 @@ int sl_cnn_apply(const sl_system *s, const float *params_dev, const void *packed
   sl::CnnPlanes pl0 = planes(s, batch, sigma_dev);
   if (!layerwise()) {
     CK(sl::cnn_copy_lowpass(coeffs_dev, coeffs_out_dev, batch, s->R, (int)s->cfg.npix(), st));
-    CK(sl::cnn_fused(coeffs_dev, pl0, P, H, W, pk.w1k, pk.w2, pk.w3, params_dev, coeffs_out_dev,
-                     gains_dev, st));
+    CK(sl::cnn_fused(coeffs_dev, pl0, P, H, W, pk.w1k, pk.w2, pk.w3m, params_dev, coeffs_out_dev,
+                     gains_dev, s->num_cu, st));
     return SL_OK;
   }
   uint16_t *A = (uint16_t *)workspace_dev;

@@ -15,6 +15,7 @@ struct sl_system {
   std::vector<double> l2, l1;
   int R = 0;
   int device = 0;
+  int num_cu = 1;                 // compute units of the device
   size_t chunk_cap = 0;
   float *d_filt = nullptr;    // 2D: [R][H][W]
   float *d_psi = nullptr;     // Psi_hat on the grid

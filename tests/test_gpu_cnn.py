@@ -85,9 +85,11 @@ def test_inverse_adjoint():
     assert abs(lhs - rhs) < 1e-5 * np.linalg.norm(c) * np.linalg.norm(an)
 
 
-def test_cnn_forward_matches_oracle():
-    print("case: cnn apply 64x64 J=2 B=2 (32 planes)", flush=True)
-    sysg, sig, c, params, pg = _setup()
+@pytest.mark.parametrize("dims", [(64, 64), (24, 48)])
+def test_cnn_forward_matches_oracle(dims):
+    # 24 x 48 leaves partial 16 x 32 output tiles in both directions
+    print(f"case: cnn apply {dims} J=2 B=2 (32 planes)", flush=True)
+    sysg, sig, c, params, pg = _setup(dims=dims)
     net = B.Shrinkage(sysg, pg)
     gains = torch.zeros_like(c)
     out = net.apply(c, _gpu(sig), gains=gains)
@@ -108,11 +110,13 @@ def test_cnn_forward_matches_oracle():
     assert np.sqrt(num / den) < 1e-3
 
 
-def test_fused_and_layerwise_inference_agree(monkeypatch):
+@pytest.mark.parametrize("dims", [(96, 192), (96, 48)])
+def test_fused_and_layerwise_inference_agree(monkeypatch, dims):
     # the fused tile kernel and the layer-by-layer path compute the same network;
-    # they differ only in the float32 summation order of layer 1
-    print("case: cnn fused vs layerwise 96x192 J=2 B=2", flush=True)
-    sysg, sig, c, params, pg = _setup(dims=(96, 192))
+    # they differ only in the float32 summation order (layer 1 packs its taps
+    # into one product, layer 3 sums per-tap partial products)
+    print(f"case: cnn fused vs layerwise {dims} J=2 B=2", flush=True)
+    sysg, sig, c, params, pg = _setup(dims=dims)
     net = B.Shrinkage(sysg, pg)
     g1 = torch.zeros_like(c)
     net.apply(c, _gpu(sig), gains=g1)
