@@ -170,6 +170,20 @@ constexpr int kLdsH1 = NH1 * CHP * 2, kLdsH2 = NH2 * CHP * 2, kLdsC = FTH * FTW 
 static_assert(NX0 * 4 <= kLdsH2, "x0 must fit in the h2 region");
 static_assert(9 * NH2 * 4 <= kLdsH1, "layer-3 partial sums must fit in the h1 region");
 
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+// relu(d + bias) on 4 channels, zero outside the image, rounded to bfloat16
+// (round to nearest even, the rounding of f2bf) by the native conversion
+__device__ __forceinline__ bf16x4 relu_bf16x4(f32x4 d, const float (&bias)[4], bool in) {
+  bf16x4 o;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const float v = d[e] + bias[e];
+    o[e] = (__bf16)((in && v > 0.f) ? v : 0.f);
+  }
+  return o;
+}
+
 struct FusedTile {
   int p, ty0, tx0, b, i, j;
 };
@@ -268,29 +282,22 @@ k_cnn_fused(const float *__restrict__ coef, CnnPlanes pl, int H, int W, int ntil
     for (int blk = wave; blk < NH1 / 16; blk += NW) {
       const int q = blk * 16 + (lane & 15);
       const int r = q / H1W, c = q % H1W;
-      uint16_t av[8];
+      // k = 8 (lane / 16) + jj = 2 t + channel: dword jj / 2 of the operand is
+      // the (channel 0, channel 1) pair of tap t = 4 (lane / 16) + jj / 2
+      uint32_t u[4];
 #pragma unroll
-      for (int jj = 0; jj < 8; jj += 2) {
-        const int t = 4 * (lane >> 4) + (jj >> 1);   // k = 8 (lane / 16) + jj = 2 t + channel
-        uint32_t v = 0u;
-        if (t < 9) v = x0s[(r + t / 3) * X0W + c + t % 3];
-        av[jj] = (uint16_t)(v & 0xFFFFu);
-        av[jj + 1] = (uint16_t)(v >> 16);
+      for (int h = 0; h < 4; ++h) {
+        const int t = 4 * (lane >> 4) + h;
+        u[h] = t < 9 ? x0s[(r + t / 3) * X0W + c + t % 3] : 0u;
       }
-      const bf16x8 xb = *(const bf16x8 *)av;
+      const bf16x8 xb = *(const bf16x8 *)u;
       const int yy = f.ty0 - 2 + r, xx = f.tx0 - 2 + c;
       const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb) {
         const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[nb], xb, f32x4{0.f, 0.f, 0.f, 0.f},
                                                                 0, 0, 0);
-        uint16_t o[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const float v = d[e] + bias1[nb][e];
-          o[e] = (in && v > 0.f) ? f2bf(v) : (uint16_t)0;
-        }
-        *(uint2 *)(h1s + q * CHP + 16 * nb + 4 * (lane >> 4)) = *(const uint2 *)o;
+        *(bf16x4 *)(h1s + q * CHP + 16 * nb + 4 * (lane >> 4)) = relu_bf16x4(d, bias1[nb], in);
       }
     }
     __syncthreads();
@@ -301,25 +308,42 @@ k_cnn_fused(const float *__restrict__ coef, CnnPlanes pl, int H, int W, int ntil
       fn = fused_tile(pl, next, tiles_x, tiles_per_plane);
       fetch(fn);
     }
-    // ---- layer 2: NH2 = 612 pixels, 39 blocks of 16 (the last has 4), two per step
+    // ---- layer 2: NH2 = 612 pixels, 39 blocks of 16 (the last has 4), two per
+    // step: four independent accumulators, the next tap's operands in flight
     for (int b0 = 2 * wave; b0 < (NH2 + 15) / 16; b0 += 2 * NW) {
-      f32x4 acc[2][2];
-      int qq[2];
+      int qq[2], base[2];
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
-        int q = (b0 + s) * 16 + (lane & 15);
+        const int q = (b0 + s) * 16 + (lane & 15);
         qq[s] = q;
-        if (q >= NH2) q = NH2 - 1;       // duplicate a valid pixel; not stored
-        const int r = q / H2W, c = q % H2W;
-        acc[s][0] = f32x4{0.f, 0.f, 0.f, 0.f};
-        acc[s][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const int qc = q < NH2 ? q : NH2 - 1;   // duplicate a valid pixel; not stored
+        base[s] = (qc / H2W) * H1W + qc % H2W;
+      }
+      f32x4 acc[2][2];
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-          const int pix = (r + t / 3) * H1W + c + t % 3;
-          const bf16x8 xb = *(const bf16x8 *)(h1s + pix * CHP + 8 * (lane >> 4));
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) acc[s][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      const uint16_t *hp = h1s + 8 * (lane >> 4);
+      bf16x8 xa[2];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) xa[s] = *(const bf16x8 *)(hp + base[s] * CHP);
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        bf16x8 xn[2];
+        if (t < 8) {
+          const int off = ((t + 1) / 3) * H1W + (t + 1) % 3;
+#pragma unroll
+          for (int s = 0; s < 2; ++s) xn[s] = *(const bf16x8 *)(hp + (base[s] + off) * CHP);
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
 #pragma unroll
           for (int nb = 0; nb < 2; ++nb)
-            acc[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[t][nb], xb, acc[s][nb], 0, 0, 0);
+            acc[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[t][nb], xa[s], acc[s][nb], 0, 0, 0);
+        if (t < 8) {
+#pragma unroll
+          for (int s = 0; s < 2; ++s) xa[s] = xn[s];
         }
       }
 #pragma unroll
@@ -330,15 +354,8 @@ k_cnn_fused(const float *__restrict__ coef, CnnPlanes pl, int H, int W, int ntil
         const int yy = f.ty0 - 1 + r, xx = f.tx0 - 1 + c;
         const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
-          uint16_t o[4];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const float v = acc[s][nb][e] + bias2[nb][e];
-            o[e] = (in && v > 0.f) ? f2bf(v) : (uint16_t)0;
-          }
-          *(uint2 *)(h2s + q * CHP + 16 * nb + 4 * (lane >> 4)) = *(const uint2 *)o;
-        }
+        for (int nb = 0; nb < 2; ++nb)
+          *(bf16x4 *)(h2s + q * CHP + 16 * nb + 4 * (lane >> 4)) = relu_bf16x4(acc[s][nb], bias2[nb], in);
       }
     }
     __syncthreads();
