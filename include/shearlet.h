@@ -137,6 +137,18 @@ int sl_denoise(const sl_system *s, const float *x_dev, int batch, const float *s
                const float *K_host, void *coeffs_dev, float *scales_dev, float *out_dev,
                void *workspace_dev, size_t workspace_bytes, void *stream);
 
+/* Hard-threshold denoising without materialising the coefficients: the
+ * forward transform's last row DFT, the threshold of eq. hard_tresholding
+ * (delta = K_j sigma_b ||psi_i||_2, lowpass kept) and the inverse transform's
+ * first row DFT run in one pass over each pair of subbands, so the K-fold
+ * coefficient tensor never reaches memory.  Arithmetic is float32 throughout:
+ * the result equals sl_denoise on an SL_F32 system (for F16/BF16 systems it
+ * omits their storage rounding).  x_dev, out_dev [B][dims] float32;
+ * sigma_dev [B] device; K_host [J] host; workspace as sl_workspace_size.     */
+int sl_denoise_fused(const sl_system *s, const float *x_dev, int batch, const float *sigma_dev,
+                     const float *K_host, float *out_dev, void *workspace_dev,
+                     size_t workspace_bytes, void *stream);
+
 /* Adjoint of sl_inverse: c_i = IDFT(psi_hat_i / Psi_hat .* DFT(r)) for every
  * subband, i.e. the forward transform with the dual filters of eq.
  * dual_filter.  Used to back-propagate an image-domain loss through the
@@ -145,7 +157,7 @@ int sl_inverse_adjoint(const sl_system *s, const float *r_dev, int batch, float 
                        void *workspace_dev, size_t workspace_bytes, void *stream);
 
 /* Bytes of the intermediate chunk of subband-pair planes that one pass
- * launch processes (default 128 MiB or $SL_CHUNK_MB).  Changing it changes
+ * launch processes (default 2 GiB or $SL_CHUNK_MB).  Changing it changes
  * sl_workspace_size.                                                        */
 int sl_system_set_chunk_bytes(sl_system *s, size_t bytes);
 size_t sl_system_chunk_bytes(const sl_system *s);

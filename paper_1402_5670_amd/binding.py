@@ -70,6 +70,9 @@ _SIGS = {
     "sl_denoise": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                     ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+    "sl_denoise_fused": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                          ctypes.c_void_p], ctypes.c_int),
     "sl_inverse_adjoint": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                             ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
     "sl_cnn_packed_bytes": ([ctypes.c_int], ctypes.c_size_t),
@@ -323,6 +326,21 @@ class System:
         check(lib().sl_denoise(self._h, _ptr(x), B, _ptr(sigma), ctypes.cast(Kh, ctypes.c_void_p),
                                _ptr(coeffs), _ptr(scales), _ptr(out), _ptr(ws), ws.numel(),
                                _stream()))
+        return out
+
+
+    def denoise_fused(self, x, sigma, K, out=None, workspace=None):
+        """Hard-threshold denoising without materialised coefficients (float32)."""
+        import torch
+        self._check_x(x)
+        B = x.shape[0]
+        if out is None:
+            out = torch.empty_like(x)
+        ws = workspace if workspace is not None else self.workspace(B, x.device)
+        Kh = (ctypes.c_float * len(K))(*[float(k) for k in K])
+        check(lib().sl_denoise_fused(self._h, _ptr(x), B, _ptr(sigma),
+                                     ctypes.cast(Kh, ctypes.c_void_p), _ptr(out), _ptr(ws),
+                                     ws.numel(), _stream()))
         return out
 
 

@@ -88,8 +88,11 @@ void chunk_plan(const sl_system *s, int B, int &nb, int &np) {
   }
 }
 
+// Workspace: spectrum F (also the inverse's accumulator) [B] complex planes,
+// a second accumulator [B] used by sl_denoise_fused (F must survive every
+// chunk there), the chunk of pair planes, per-image max |x|.
 struct Layout {
-  size_t off_F, off_chunk, off_xmax, total;
+  size_t off_F, off_acc, off_chunk, off_xmax, total;
 };
 
 Layout layout(const sl_system *s, int B) {
@@ -98,7 +101,8 @@ Layout layout(const sl_system *s, int B) {
   const size_t plane = 8ull * (size_t)s->cfg.npix();
   Layout L;
   L.off_F = 0;
-  L.off_chunk = align_up(plane * B);
+  L.off_acc = align_up(plane * B);
+  L.off_chunk = align_up(L.off_acc + plane * B);
   L.off_xmax = align_up(L.off_chunk + plane * (size_t)nb * np);
   L.total = align_up(L.off_xmax + 4ull * B);
   return L;
@@ -170,11 +174,12 @@ enum Pass {
   P_COLS_FFT_ACC,
   P_ROWS_REAL_IFFT,
   P_AUX,
+  P_ROWS_THR,
   P_COUNT
 };
 const char *kPassNames[P_COUNT] = {"rows_real_fft",   "cols_fft",      "cols_filter_ifft",
                                    "rows_coef",       "rows_coef_fft", "cols_fft_acc",
-                                   "rows_real_ifft",  "aux"};
+                                   "rows_real_ifft",  "aux",           "rows_thr"};
 
 struct Timing {
   bool on = false;
@@ -522,6 +527,65 @@ int sl_inverse(const sl_system *s, const void *coeffs_dev, const float *scales_d
       SL_LAUNCH(P_COLS_FFT_ACC, st, sl::launch_cols_fft_acc(v, U, ACC, c, p0 == 0, p0 + c.np == P, st));
     }
   SL_LAUNCH(P_ROWS_REAL_IFFT, st, sl::launch_rows_real_ifft(v, ACC, x_dev, batch, st));
+  return SL_OK;
+}
+
+int sl_denoise_fused(const sl_system *s, const float *x_dev, int batch, const float *sigma_dev,
+                     const float *K_host, float *out_dev, void *workspace_dev,
+                     size_t workspace_bytes, void *stream) {
+  int rc = check_call(s, batch, x_dev, out_dev, workspace_dev, workspace_bytes);
+  if (rc) return rc;
+  if (!sigma_dev || !K_host) return fail(SL_EINVAL, "sigma_dev and K_host are required");
+  if (s->cfg.J > sl::kMaxScales) return fail(SL_EUNSUPPORTED, "too many scales");
+  sl::ThrArgs thr{};
+  thr.sigma = sigma_dev;
+  thr.l2 = s->d_l2;
+  thr.jof = s->d_jof;
+  for (int j = 0; j < s->cfg.J; ++j) thr.K[j] = K_host[j];
+  hipStream_t st = (hipStream_t)stream;
+  const Layout L = layout(s, batch);
+  char *ws = (char *)workspace_dev;
+  float2 *F = (float2 *)(ws + L.off_F);
+  float2 *ACC = (float2 *)(ws + L.off_acc);
+  float2 *T = (float2 *)(ws + L.off_chunk);
+  const float inv_n = 1.0f / (float)s->cfg.npix();
+  int nb, np;
+  chunk_plan(s, batch, nb, np);
+  const int P = (s->R + 1) / 2;
+  if (s->cfg.ndim == 3) {
+    const int D = (int)s->cfg.dims[0], H = (int)s->cfg.dims[1], W = (int)s->cfg.dims[2];
+    const sl::Sys2D vr = view2d(s, D * H, W, 0, W);
+    const sl::Sys2D vy = view2d(s, H, W, H, 0);
+    const sl::Sys2D vz = view2d(s, D, H * W, D, 0);
+    const sl::Sys3D v3 = view3d(s);
+    SL_LAUNCH(P_ROWS_REAL_FFT, st, sl::launch_rows_real_fft(vr, x_dev, F, nullptr, batch, st));
+    SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, F, F, batch * D, false, st));
+    SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vz, F, F, batch, false, st));
+    for (int b0 = 0; b0 < batch; b0 += nb)
+      for (int p0 = 0; p0 < P; p0 += np) {
+        sl::Chunk c{b0, std::min(nb, batch - b0), p0, std::min(np, P - p0)};
+        SL_LAUNCH(P_COLS_FILTER_IFFT, st, sl::launch_z_filter_ifft(v3, F, T, c, st));
+        SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, T, T, c.nb * c.np * D, true, st));
+        SL_LAUNCH(P_ROWS_THR, st, sl::launch_rows_thr(vr, T, inv_n, c, thr, st));
+        SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, T, T, c.nb * c.np * D, false, st));
+        SL_LAUNCH(P_COLS_FFT_ACC, st,
+                  sl::launch_z_fft_acc(v3, T, ACC, c, p0 == 0, p0 + c.np == P, st));
+      }
+    SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, ACC, ACC, batch * D, true, st));
+    SL_LAUNCH(P_ROWS_REAL_IFFT, st, sl::launch_rows_real_ifft(vr, ACC, out_dev, batch, st));
+    return SL_OK;
+  }
+  const sl::Sys2D v = view2d(s);
+  SL_LAUNCH(P_ROWS_REAL_FFT, st, sl::launch_rows_real_fft(v, x_dev, F, nullptr, batch, st));
+  SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(v, F, F, batch, false, st));
+  for (int b0 = 0; b0 < batch; b0 += nb)
+    for (int p0 = 0; p0 < P; p0 += np) {
+      sl::Chunk c{b0, std::min(nb, batch - b0), p0, std::min(np, P - p0)};
+      SL_LAUNCH(P_COLS_FILTER_IFFT, st, sl::launch_cols_filter_ifft(v, F, T, c, st));
+      SL_LAUNCH(P_ROWS_THR, st, sl::launch_rows_thr(v, T, inv_n, c, thr, st));
+      SL_LAUNCH(P_COLS_FFT_ACC, st, sl::launch_cols_fft_acc(v, T, ACC, c, p0 == 0, p0 + c.np == P, st));
+    }
+  SL_LAUNCH(P_ROWS_REAL_IFFT, st, sl::launch_rows_real_ifft(v, ACC, out_dev, batch, st));
   return SL_OK;
 }
 

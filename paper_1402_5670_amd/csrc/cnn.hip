@@ -156,30 +156,45 @@ k_conv3x3(const uint16_t *__restrict__ in, const uint16_t *__restrict__ Wp,
 // b3 + sum_t D[t][p + offset(t)].
 // h1 and h2 pixels are padded to 40 channels (80 bytes), which spreads the
 // 16 pixels of an operand read over distinct LDS banks.
-constexpr int FTH = 16, FTW = 32;
+// Output tile FTH x 32 (SL_CNN_FTH = 16 or 8), one thread per output pixel;
+// pixel stride of h1 and h2 SL_CNN_CHP bfloat16 values (>= 32).
+#ifndef SL_CNN_FTH
+#define SL_CNN_FTH 16
+#endif
+#ifndef SL_CNN_CHP
+#define SL_CNN_CHP 40
+#endif
+constexpr int FTH = SL_CNN_FTH, FTW = 32;
 constexpr int X0H = FTH + 6, X0W = FTW + 6;
 constexpr int H1H = FTH + 4, H1W = FTW + 4;
 constexpr int H2H = FTH + 2, H2W = FTW + 2;
 constexpr int NX0 = X0H * X0W, NH1 = H1H * H1W, NH2 = H2H * H2W;
-constexpr int CHP = 40;
-constexpr int kFusedThreads = 512;
+constexpr int CHP = SL_CNN_CHP;
+constexpr int kFusedThreads = FTH * FTW;
+static_assert(NH1 % 16 == 0 && CHP % 4 == 0 && CHP >= 32, "tile geometry");
 constexpr int kX0PerThread = (NX0 + kFusedThreads - 1) / kFusedThreads;
 // LDS (bytes): h1 | h2 (x0 shares it) | 2 x raw centre coefficients.  The
-// layer-3 partial sums D[9][NH2] reuse the h1 region once layer 2 is done.
+// layer-3 partial sums D[16][NH2] reuse the h1 region once layer 2 is done.
 constexpr int kLdsH1 = NH1 * CHP * 2, kLdsH2 = NH2 * CHP * 2, kLdsC = FTH * FTW * 4;
 static_assert(NX0 * 4 <= kLdsH2, "x0 must fit in the h2 region");
-static_assert(9 * NH2 * 4 <= kLdsH1, "layer-3 partial sums must fit in the h1 region");
+static_assert(16 * NH2 * 4 <= kLdsH1, "layer-3 partial sums must fit in the h1 region");
+// blocks of the persistent grid per compute unit (160 KiB of LDS each)
+constexpr int kFusedBlocksPerCU = (2 * (kLdsH1 + kLdsH2 + 2 * kLdsC) <= 160 * 1024) ? 2 : 1;
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
-// relu(d + bias) on 4 channels, zero outside the image, rounded to bfloat16
-// (round to nearest even, the rounding of f2bf) by the native conversion
-__device__ __forceinline__ bf16x4 relu_bf16x4(f32x4 d, const float (&bias)[4], bool in) {
+// relu(d) on 4 channels (the bias is the accumulator's initial value), zero
+// outside the image, rounded to bfloat16 (round to nearest even, as f2bf) by
+// the native conversion
+// (relu as a signed integer maximum of the float bits: negative floats have
+// the sign bit set, so max(bits, 0) maps them to +0 and keeps the others)
+template <bool INTERIOR>
+__device__ __forceinline__ bf16x4 relu_bf16x4(f32x4 d, bool in) {
   bf16x4 o;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    const float v = d[e] + bias[e];
-    o[e] = (__bf16)((in && v > 0.f) ? v : 0.f);
+    const float v = __int_as_float(max(__float_as_int(d[e]), 0));
+    o[e] = (__bf16)((INTERIOR || in) ? v : 0.f);
   }
   return o;
 }
@@ -199,6 +214,11 @@ __device__ __forceinline__ FusedTile fused_tile(const CnnPlanes &pl, int tile, i
   return f;
 }
 
+template <int V>
+struct IntC {
+  static constexpr int value = V;
+};
+
 __global__ void __launch_bounds__(kFusedThreads)
 k_cnn_fused(const float *__restrict__ coef, CnnPlanes pl, int H, int W, int ntiles,
             const uint16_t *__restrict__ W1k, const uint16_t *__restrict__ W2p,
@@ -210,21 +230,29 @@ k_cnn_fused(const float *__restrict__ coef, CnnPlanes pl, int H, int W, int ntil
   uint16_t *h2s = (uint16_t *)(smem + kLdsH1);
   uint32_t *x0s = (uint32_t *)(smem + kLdsH1);       // before layer 2
   float *cs = (float *)(smem + kLdsH1 + kLdsH2);     // [2][FTH * FTW]
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4;
   constexpr int NW = kFusedThreads / 64;
   const int tiles_x = (W + FTW - 1) / FTW;
   const int tiles_per_plane = tiles_x * ((H + FTH - 1) / FTH);
   const size_t HWn = (size_t)H * W;
 
-  // stage the x0 region of a tile: registers hold raw coefficients (0 outside)
+  // x0 staging: thread positions in the x0 region do not depend on the tile
+  int xq_r[kX0PerThread], xq_c[kX0PerThread], xq_cs[kX0PerThread];
+#pragma unroll
+  for (int u = 0; u < kX0PerThread; ++u) {
+    const int q = threadIdx.x + u * kFusedThreads;
+    xq_r[u] = q < NX0 ? q / X0W : -1000;
+    xq_c[u] = q % X0W;
+    const int r = xq_r[u], c = xq_c[u];
+    xq_cs[u] = (r >= 3 && r < 3 + FTH && c >= 3 && c < 3 + FTW) ? (r - 3) * FTW + c - 3 : -1;
+  }
   float xr[kX0PerThread];
   auto fetch = [&](const FusedTile &f) {
     const float *cpl = coef + ((size_t)f.b * pl.R + f.i) * HWn;
 #pragma unroll
     for (int u = 0; u < kX0PerThread; ++u) {
-      const int q = threadIdx.x + u * kFusedThreads;
-      const int yy = f.ty0 - 3 + q / X0W, xx = f.tx0 - 3 + q % X0W;
-      xr[u] = (q < NX0 && yy >= 0 && yy < H && xx >= 0 && xx < W) ? cpl[(size_t)yy * W + xx] : 0.f;
+      const int yy = f.ty0 - 3 + xq_r[u], xx = f.tx0 - 3 + xq_c[u];
+      xr[u] = (yy >= 0 && yy < H && xx >= 0 && xx < W) ? cpl[(size_t)yy * W + xx] : 0.f;
     }
   };
   auto stage = [&](const FusedTile &f, int buf) {
@@ -233,19 +261,31 @@ k_cnn_fused(const float *__restrict__ coef, CnnPlanes pl, int H, int W, int ntil
     const uint32_t ch1 = (uint32_t)f2bf(sg * (255.0f / 50.0f)) << 16;
 #pragma unroll
     for (int u = 0; u < kX0PerThread; ++u) {
+      if (xq_r[u] < 0) continue;
       const int q = threadIdx.x + u * kFusedThreads;
-      if (q >= NX0) continue;
-      const int r = q / X0W, c = q % X0W;
-      const int yy = f.ty0 - 3 + r, xx = f.tx0 - 3 + c;
+      // out-of-image positions were fetched as 0; their x0 must be 0 in both channels
+      const int yy = f.ty0 - 3 + xq_r[u], xx = f.tx0 - 3 + xq_c[u];
       const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
       x0s[q] = in ? ((uint32_t)f2bf(fabsf(xr[u]) * inv) | ch1) : 0u;
-      if (r >= 3 && r < 3 + FTH && c >= 3 && c < 3 + FTW) cs[buf * FTH * FTW + (r - 3) * FTW + c - 3] = xr[u];
+      if (xq_cs[u] >= 0) cs[buf * FTH * FTW + xq_cs[u]] = xr[u];
     }
   };
 
-  // weights of the current scale (reloaded when the scale changes)
+  // layer-1 operand: dword h of a lane's K slice is the (channel 0, channel 1)
+  // pair of tap t = 4 g + h (k = 8 g + 2 h + channel).  Slots of taps >= 9
+  // have zero weights; they read tap 0 (a staged, finite value) instead.
+  int toff[4];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const int t = 4 * g + h;
+    toff[h] = t < 9 ? (t / 3) * X0W + t % 3 : 0;
+  }
+
+  // weights of the current scale (reloaded when the scale changes); the
+  // biases become the accumulators' initial values
   bf16x8 w1[2], w2[9][2], w3;
-  float bias1[2][4], bias2[2][4], b3 = 0.f;
+  f32x4 bias1[2], bias2[2];
+  float b3 = 0.f;
   int cur_j = -1;
   auto load_weights = [&](int j) {
     const float *P = params + (size_t)j * kCnnParams;
@@ -257,13 +297,127 @@ k_cnn_fused(const float *__restrict__ coef, CnnPlanes pl, int H, int W, int ntil
         w2[t][nb] = *(const bf16x8 *)(W2p + ((((size_t)j * 9 + t) * 2 + nb) * 64 + lane) * 8);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int ch = 16 * nb + 4 * (lane >> 4) + q;
+        const int ch = 16 * nb + 4 * g + q;
         bias1[nb][q] = P[kOffB1 + ch];
         bias2[nb][q] = P[kOffB2 + ch];
       }
     }
     w3 = *(const bf16x8 *)(W3m + ((size_t)j * 64 + lane) * 8);
     b3 = P[kOffB3];
+  };
+
+  // the three layers and the output of tile f; INTERIOR: the x0 region lies
+  // inside the image, so no activation needs the zero padding mask
+  auto layers = [&](const FusedTile &f, int buf, auto interior) {
+    constexpr bool INTERIOR = decltype(interior)::value != 0;
+    // ---- layer 1: NH1 pixels in blocks of 16
+    for (int blk = wave; blk < NH1 / 16; blk += NW) {
+      const int q = blk * 16 + (lane & 15);
+      const int r = q / H1W, c = q % H1W;
+      const int base = r * X0W + c;
+      uint32_t u[4];
+#pragma unroll
+      for (int h = 0; h < 4; ++h) u[h] = x0s[base + toff[h]];
+      const bf16x8 xb = *(const bf16x8 *)u;
+      bool in = true;
+      if constexpr (!INTERIOR) {
+        const int yy = f.ty0 - 2 + r, xx = f.tx0 - 2 + c;
+        in = yy >= 0 && yy < H && xx >= 0 && xx < W;
+      }
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[nb], xb, bias1[nb], 0, 0, 0);
+        *(bf16x4 *)(h1s + q * CHP + 16 * nb + 4 * g) = relu_bf16x4<INTERIOR>(d, in);
+      }
+    }
+    __syncthreads();
+    // ---- layer 2: NH2 pixels in NB2 blocks of 16 (the last may be partial).
+    // Wave w of NW takes blocks w, w + NW, w + 2 NW, ..., two at a time (four
+    // independent accumulators, the next tap's operands in flight)
+    constexpr int NB2 = (NH2 + 15) / 16;
+    auto l2 = [&](int bA, auto count) {
+      constexpr int S = decltype(count)::value;
+      int qq[S], base[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int q = (bA + NW * s) * 16 + (lane & 15);
+        qq[s] = q;
+        const int qc = q < NH2 ? q : NH2 - 1;   // duplicate a valid pixel; not stored
+        base[s] = (qc / H2W) * H1W + qc % H2W;
+      }
+      f32x4 acc[S][2];
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) acc[s][nb] = bias2[nb];
+      const uint16_t *hp = h1s + 8 * g;
+      bf16x8 xa[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) xa[s] = *(const bf16x8 *)(hp + base[s] * CHP);
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        bf16x8 xn[S];
+        if (t < 8) {
+          const int off = ((t + 1) / 3) * H1W + (t + 1) % 3;
+#pragma unroll
+          for (int s = 0; s < S; ++s) xn[s] = *(const bf16x8 *)(hp + (base[s] + off) * CHP);
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb)
+            acc[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[t][nb], xa[s], acc[s][nb], 0, 0, 0);
+        if (t < 8) {
+#pragma unroll
+          for (int s = 0; s < S; ++s) xa[s] = xn[s];
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int q = qq[s];
+        if (q >= NH2) continue;
+        bool in = true;
+        if constexpr (!INTERIOR) {
+          const int r = q / H2W, c = q % H2W;
+          const int yy = f.ty0 - 1 + r, xx = f.tx0 - 1 + c;
+          in = yy >= 0 && yy < H && xx >= 0 && xx < W;
+        }
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+          *(bf16x4 *)(h2s + q * CHP + 16 * nb + 4 * g) = relu_bf16x4<INTERIOR>(acc[s][nb], in);
+      }
+    };
+    for (int bA = wave; bA < NB2; bA += 2 * NW) {
+      if (bA + NW < NB2) l2(bA, IntC<2>{});
+      else l2(bA, IntC<1>{});
+    }
+    __syncthreads();
+    // ---- layer 3, per-tap partial sums over the 32 channels of every h2 pixel;
+    // taps 9..15 have zero weights and land in unused rows of d3
+    for (int blk = wave; blk < NB2; blk += NW) {
+      const int q = blk * 16 + (lane & 15);
+      const int qc = q < NH2 ? q : NH2 - 1;
+      const bf16x8 xb = *(const bf16x8 *)(h2s + qc * CHP + 8 * g);
+      const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3, xb, f32x4{0.f, 0.f, 0.f, 0.f},
+                                                              0, 0, 0);
+      if (q < NH2) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) d3[(4 * g + e) * NH2 + q] = d[e];
+      }
+    }
+    __syncthreads();
+    // ---- output: one pixel per thread
+    const int r = threadIdx.x / FTW, c = threadIdx.x % FTW;
+    float z = b3;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) z += d3[t * NH2 + (r + t / 3) * H2W + c + t % 3];
+    const int yy = f.ty0 + r, xx = f.tx0 + c;
+    if (INTERIOR || (yy < H && xx < W)) {
+      const float gv = 1.0f / (1.0f + __expf(-z));
+      const size_t co = ((size_t)f.b * pl.R + f.i) * HWn + (size_t)yy * W + xx;
+      if (gain) gain[co] = gv;
+      coef_out[co] = gv * cs[buf * FTH * FTW + threadIdx.x];
+    }
   };
 
   int tile = blockIdx.x;
@@ -278,119 +432,18 @@ k_cnn_fused(const float *__restrict__ coef, CnnPlanes pl, int H, int W, int ntil
       load_weights(f.j);
       cur_j = f.j;
     }
-    // ---- layer 1: NH1 = 720 pixels, 45 blocks of 16
-    for (int blk = wave; blk < NH1 / 16; blk += NW) {
-      const int q = blk * 16 + (lane & 15);
-      const int r = q / H1W, c = q % H1W;
-      // k = 8 (lane / 16) + jj = 2 t + channel: dword jj / 2 of the operand is
-      // the (channel 0, channel 1) pair of tap t = 4 (lane / 16) + jj / 2
-      uint32_t u[4];
-#pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        const int t = 4 * (lane >> 4) + h;
-        u[h] = t < 9 ? x0s[(r + t / 3) * X0W + c + t % 3] : 0u;
-      }
-      const bf16x8 xb = *(const bf16x8 *)u;
-      const int yy = f.ty0 - 2 + r, xx = f.tx0 - 2 + c;
-      const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb) {
-        const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[nb], xb, f32x4{0.f, 0.f, 0.f, 0.f},
-                                                                0, 0, 0);
-        *(bf16x4 *)(h1s + q * CHP + 16 * nb + 4 * (lane >> 4)) = relu_bf16x4(d, bias1[nb], in);
-      }
-    }
-    __syncthreads();
-    // prefetch the next tile's coefficients; they land during layers 2 and 3
+    // prefetch the next tile's coefficients; they land during the layers
     const int next = tile + gridDim.x;
     FusedTile fn = f;
     if (next < ntiles) {
       fn = fused_tile(pl, next, tiles_x, tiles_per_plane);
       fetch(fn);
     }
-    // ---- layer 2: NH2 = 612 pixels, 39 blocks of 16 (the last has 4), two per
-    // step: four independent accumulators, the next tap's operands in flight
-    for (int b0 = 2 * wave; b0 < (NH2 + 15) / 16; b0 += 2 * NW) {
-      int qq[2], base[2];
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const int q = (b0 + s) * 16 + (lane & 15);
-        qq[s] = q;
-        const int qc = q < NH2 ? q : NH2 - 1;   // duplicate a valid pixel; not stored
-        base[s] = (qc / H2W) * H1W + qc % H2W;
-      }
-      f32x4 acc[2][2];
-#pragma unroll
-      for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) acc[s][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-      const uint16_t *hp = h1s + 8 * (lane >> 4);
-      bf16x8 xa[2];
-#pragma unroll
-      for (int s = 0; s < 2; ++s) xa[s] = *(const bf16x8 *)(hp + base[s] * CHP);
-#pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        bf16x8 xn[2];
-        if (t < 8) {
-          const int off = ((t + 1) / 3) * H1W + (t + 1) % 3;
-#pragma unroll
-          for (int s = 0; s < 2; ++s) xn[s] = *(const bf16x8 *)(hp + (base[s] + off) * CHP);
-        }
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-          for (int nb = 0; nb < 2; ++nb)
-            acc[s][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[t][nb], xa[s], acc[s][nb], 0, 0, 0);
-        if (t < 8) {
-#pragma unroll
-          for (int s = 0; s < 2; ++s) xa[s] = xn[s];
-        }
-      }
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const int q = qq[s];
-        if (q >= NH2) continue;
-        const int r = q / H2W, c = q % H2W;
-        const int yy = f.ty0 - 1 + r, xx = f.tx0 - 1 + c;
-        const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
-          *(bf16x4 *)(h2s + q * CHP + 16 * nb + 4 * (lane >> 4)) = relu_bf16x4(acc[s][nb], bias2[nb], in);
-      }
-    }
-    __syncthreads();
-    // ---- layer 3, per-tap partial sums over the 32 channels of every h2 pixel
-    for (int blk = wave; blk < (NH2 + 15) / 16; blk += NW) {
-      const int q = blk * 16 + (lane & 15);
-      const int qc = q < NH2 ? q : NH2 - 1;
-      const bf16x8 xb = *(const bf16x8 *)(h2s + qc * CHP + 8 * (lane >> 4));
-      const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3, xb, f32x4{0.f, 0.f, 0.f, 0.f},
-                                                              0, 0, 0);
-      if (q < NH2) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int t = 4 * (lane >> 4) + e;
-          if (t < 9) d3[t * NH2 + q] = d[e];
-        }
-      }
-    }
-    __syncthreads();
-    // ---- output: one pixel per thread
-    {
-      const int r = threadIdx.x / FTW, c = threadIdx.x % FTW;
-      float z = b3;
-#pragma unroll
-      for (int t = 0; t < 9; ++t) z += d3[t * NH2 + (r + t / 3) * H2W + c + t % 3];
-      const int yy = f.ty0 + r, xx = f.tx0 + c;
-      if (yy < H && xx < W) {
-        const float g = 1.0f / (1.0f + __expf(-z));
-        const size_t co = ((size_t)f.b * pl.R + f.i) * HWn + (size_t)yy * W + xx;
-        if (gain) gain[co] = g;
-        coef_out[co] = g * cs[buf * FTH * FTW + threadIdx.x];
-      }
-    }
+    const bool interior = f.ty0 >= 3 && f.ty0 + FTH + 3 <= H && f.tx0 >= 3 && f.tx0 + FTW + 3 <= W;
+    if (interior) layers(f, buf, IntC<1>{});
+    else layers(f, buf, IntC<0>{});
     if (next >= ntiles) break;
-    // h2 reads ended at the barrier above: stage the next tile into x0 / cs
+    // h2 reads ended at the last barrier: stage the next tile into x0 / cs
     buf ^= 1;
     stage(fn, buf);
     tile = next;
@@ -592,6 +645,7 @@ hipError_t cnn_fused(const float *coef, const CnnPlanes &pl, int P, int H, int W
                      const float *params, float *coef_out, float *gain, int nblocks,
                      hipStream_t st) {
   const int ntiles = P * ((W + FTW - 1) / FTW) * ((H + FTH - 1) / FTH);
+  nblocks *= kFusedBlocksPerCU;
   const int grid = nblocks < ntiles ? nblocks : ntiles;
   if (grid < 1) return hipSuccess;
   hipLaunchKernelGGL(k_cnn_fused, dim3(grid), dim3(kFusedThreads), 0, st, coef, pl, H, W, ntiles,

@@ -44,8 +44,8 @@ hipError_t cnn_conv(const uint16_t *in, const uint16_t *Wp, int NB, const float 
                     int bias_stride, const CnnPlanes &pl, int P, int H, int W, int mode,
                     uint16_t *out, const uint16_t *mask, const float *coef, float *coef_out,
                     float *gain, hipStream_t st);
-// fused inference over P planes; a persistent grid of nblocks blocks (one
-// per compute unit: the kernel needs 107 KiB of LDS) walks the 16 x 32 tiles
+// fused inference over P planes; a persistent grid (one or two blocks per
+// compute unit, by LDS size; nblocks = compute units) walks the output tiles
 hipError_t cnn_fused(const float *coef, const CnnPlanes &pl, int P, int H, int W,
                      const uint16_t *W1k, const uint16_t *W2p, const uint16_t *W3m,
                      const float *params, float *coef_out, float *gain, int nblocks,

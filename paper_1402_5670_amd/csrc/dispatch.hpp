@@ -57,6 +57,10 @@ hipError_t launch_div_psi(float2 *F, const float *psi, size_t npix, int B, hipSt
 // coefficients -> U[chunk] (decode, threshold, pair pack, row DFT)
 hipError_t launch_rows_coef_fft(const Sys2D &s, const void *coef, const float *scales, float2 *U,
                                 Chunk c, const ThrArgs &thr, hipStream_t st);
+// T[chunk] -> T[chunk] in place: row IDFT, scale inv_n, hard threshold, row DFT
+// (denoising without materialised coefficients)
+hipError_t launch_rows_thr(const Sys2D &s, float2 *T, float inv_n, Chunk c, const ThrArgs &thr,
+                           hipStream_t st);
 // U[chunk] -> ACC (column DFT, multiply by the filter pair, sum over pairs);
 // the last chunk divides by Psi_hat and applies the column inverse DFT.
 hipError_t launch_cols_fft_acc(const Sys2D &s, const float2 *U, float2 *ACC, Chunk c, bool first,

@@ -322,6 +322,54 @@ k_rows_coef_fft(const typename Store<DT>::T *__restrict__ coef, const float *__r
   }
 }
 
+// Denoising without materialised coefficients: the forward transform's last
+// row pass and the inverse transform's first row pass on one row of a pair
+// plane.  T holds the column-transformed pair (c_a + i c_b before its row
+// IDFT); the row IDFT scaled by 1/n gives the float32 coefficients exactly as
+// k_rows_coef stores them, the hard threshold of k_rows_coef_fft is applied,
+// and the row DFT of the thresholded pair is written back in place (it is
+// the U of the inverse's column pass).
+template <int N>
+__global__ void __launch_bounds__(Tile<N>::THREADS)
+k_rows_thr(float2 *__restrict__ T, int H, int R, int b0, int p0, int np, float inv_n, ThrArgs thr,
+           const float2 *__restrict__ tw) {
+  constexpr int NT = Tile<N>::NT, M = Tile<N>::M, E = Tile<N>::E;
+  __shared__ float2 lds[M * row_lds_len<N>()];
+  const int t = threadIdx.x % NT, m = threadIdx.x / NT;
+  const int row = blockIdx.x * M + m;
+  const bool ok = row < H;
+  const int rr = ok ? row : 0;
+  const int pp = blockIdx.y, bl = blockIdx.z, b = b0 + bl;
+  const int ia = 2 * (p0 + pp), ib = ia + 1;
+  float da = 0.f, db = 0.f;
+  {
+    const float sg = thr.sigma[b];
+    const int ja = thr.jof[ia];
+    if (ja >= 0) da = (thr.K[ja] * sg) * thr.l2[ia];
+    if (ib < R) {
+      const int jb = thr.jof[ib];
+      if (jb >= 0) db = (thr.K[jb] * sg) * thr.l2[ib];
+    }
+  }
+  float2 *Ti = T + ((size_t)bl * np + pp) * (size_t)H * N + (size_t)rr * N;
+  float2 v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = Ti[t + e * NT];
+  fft_line<N, true>(v, t, LdsLine{lds + m * row_lds_len<N>(), 0}, tw);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    float a = v[e].x * inv_n, bb = ib < R ? v[e].y * inv_n : 0.f;
+    if (!(fabsf(a) >= da)) a = 0.f;
+    if (!(fabsf(bb) >= db)) bb = 0.f;
+    v[e] = make_float2(a, bb);
+  }
+  fft_line<N, false>(v, t, LdsLine{lds + m * row_lds_len<N>(), 0}, tw);
+  if (ok) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) Ti[t + e * NT] = v[e];
+  }
+}
+
 template <int N, int BT>
 __global__ void __launch_bounds__(CTile<N>::THREADS)
 k_cols_fft_acc(const float2 *__restrict__ U, const float *__restrict__ filt,
@@ -559,6 +607,22 @@ hipError_t launch_rows_coef_fft(const Sys2D &s, const void *coef, const float *s
   if (s.dtype == 1) return rows_coef_fft_dt<1>(s, coef, scales, U, c, thr, st);
   if (s.dtype == 2) return rows_coef_fft_dt<2>(s, coef, scales, U, c, thr, st);
   return rows_coef_fft_dt<0>(s, coef, scales, U, c, thr, st);
+}
+
+hipError_t launch_rows_thr(const Sys2D &s, float2 *T, float inv_n, Chunk c, const ThrArgs &thr,
+                           hipStream_t st) {
+  switch (s.W) {
+#define X(N)                                                                                   \
+  case N:                                                                                      \
+    hipLaunchKernelGGL(k_rows_thr<N>, row_grid<N>(s.H, c.np, c.nb), dim3(Tile<N>::THREADS), 0, \
+                       st, T, s.H, s.R, c.b0, c.p0, c.np, inv_n, thr, s.twW);                  \
+    break;
+    SL_FOR_EACH_N(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_cols_fft_acc(const Sys2D &s, const float2 *U, float2 *ACC, Chunk c, bool first,

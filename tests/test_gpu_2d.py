@@ -155,6 +155,35 @@ def test_hard_threshold_exact_mask():
         assert T.psnr(pairs[b][0], out[b].cpu().numpy()) > T.psnr(pairs[b][0], xs[b])
 
 
+@pytest.mark.parametrize("dims,J,levels,Bn,chunk_mb", [
+    ((256, 256), 2, [1, 1], 4, None),
+    ((256, 256), 2, [1, 1], 4, 1),          # several chunks: pair planes split
+    ((24, 96), 3, [1, 1, 2], 3, None),      # ragged row tiles
+])
+def test_denoise_fused_matches(monkeypatch, dims, J, levels, Bn, chunk_mb):
+    # no coefficient tensor: same float32 arithmetic as sl_forward + threshold +
+    # sl_inverse on an SL_F32 system, so the outputs agree to rounding (in practice
+    # bitwise); the unfused path is pinned to the oracle by the exact-mask test
+    print(f"case: fused denoise {dims} J={J} B={Bn} chunk={chunk_mb}", flush=True)
+    if chunk_mb:
+        monkeypatch.setenv("SL_CHUNK_MB", str(chunk_mb))
+    sig = np.array([0.05 + 0.05 * b for b in range(Bn)], dtype=np.float32)
+    xs = np.stack([syn.noisy_cartoon2d(*dims, 40 + b, float(sig[b]))[1] for b in range(Bn)])
+    K = np.array([3.0] * (J - 1) + [4.0], dtype=np.float32)
+    sysg = B.System(dims, J, levels)
+    xg, sg = _gpu(xs), _gpu(sig)
+    ref = sysg.denoise(xg, sg, K)
+    got = sysg.denoise_fused(xg, sg, K)
+    torch.cuda.synchronize()
+    r, g = ref.cpu().numpy(), got.cpu().numpy()
+    print(f"max |fused - unfused| = {np.max(np.abs(g - r)):.3e}", flush=True)
+    assert rel(g, r) < 1e-6
+    with pytest.raises(B.ShearletError):
+        B.check(B.lib().sl_denoise_fused(sysg._h, B._ptr(xg), Bn, None, None, B._ptr(got),
+                                         B._ptr(sysg.workspace(Bn, DEV)), sysg.workspace_bytes(Bn),
+                                         None))
+
+
 def test_chunked_schedule_matches(monkeypatch):
     print("case: chunk size 1 MiB vs default", flush=True)
     x = np.random.default_rng(9).standard_normal((3, 64, 64))

@@ -102,3 +102,17 @@ def test_3d_half_storage_and_threshold():
     ref = T.inverse(ct, o.filters, o.dual_weight)
     assert rel(out.cpu().numpy()[0], ref) < 1e-5
     assert T.psnr(clean, out.cpu().numpy()[0]) > T.psnr(clean, x)
+
+
+def test_3d_denoise_fused_matches():
+    print("case: 32^3 J=2 d=[1,1] fused denoise", flush=True)
+    dims = (32, 32, 32)
+    _, x = syn.noisy_cartoon3d(*dims, 3002, 0.1)
+    s32 = B.System(dims, 2, [1, 1])
+    K = np.array([3.0, 4.0], dtype=np.float32)
+    sig = _gpu(np.array([0.1, 0.1], dtype=np.float32))
+    xg = _gpu(np.stack([x, x[::-1].copy()]))
+    ref = s32.denoise(xg, sig, K)
+    got = s32.denoise_fused(xg, sig, K)
+    torch.cuda.synchronize()
+    assert rel(got.cpu().numpy(), ref.cpu().numpy()) < 1e-6
