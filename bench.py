@@ -107,6 +107,86 @@ def cpu_baseline(seconds, sigmas, K, H, W, J, levels):
                        f"(numpy.fft, single thread), filter build excluded, {el:.1f} s")
 
 
+def time_call(fn, reps):
+    """Mean milliseconds of fn() over reps calls (device events, one warm-up)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def other_configs(reps=10):
+    """The other hot-path configurations, timed on the same GPU (not the
+    headline): FP16 coefficient storage on the 32 x 512^2 batch, the 128^3
+    volume, and the uneven batch of 64 images replayed from its HIP graph."""
+    import numpy as np
+    import torch
+    from paper_1402_5670_amd import binding as Bd
+    from paper_1402_5670_amd import synthetic as syn
+    dev = torch.device("cuda:0")
+    out = {}
+    # 32 x 512^2, R = 49, FP16 storage with per-subband scales, threshold fused
+    Bn, H, W, J, levels, K = (WORKLOAD[k] for k in ("B", "H", "W", "J", "levels", "K"))
+    sig = syn.batch_sigmas(Bn)
+    x = torch.from_numpy(np.stack([syn.noisy_cartoon2d(H, W, 2000 + b, float(sig[b]))[1]
+                                   for b in range(Bn)]).astype(np.float32)).to(dev)
+    sg = torch.from_numpy(sig.astype(np.float32)).to(dev)
+    s16 = Bd.System((H, W), J, levels, dtype="f16")
+    c, sc = s16.alloc_coeffs(Bn, dev)
+    o = torch.empty_like(x)
+    ws = s16.workspace(Bn, dev)
+    ms = time_call(lambda: (s16.forward(x, c, sc, workspace=ws),
+                            s16.inverse(c, sc, sigma=sg, K=K, out=o, workspace=ws)), reps)
+    n = Bn * s16.R * H * W
+    out["f16_storage_32x512"] = {"ms_per_step": round(ms, 4), "coefficients_per_s": n / ms * 1e3,
+                                 "hbm_algorithmic_GBps": (2 * 2 * n + 2 * 4 * Bn * H * W) / ms / 1e6}
+    del x, c, sc, o, ws, s16
+    # 128^3 volume, J = 2, levels [1, 1] (R = 99), forward + inverse
+    dims = (128, 128, 128)
+    v = torch.from_numpy(syn.noisy_cartoon3d(*dims, 3000, 0.1)[1][None].astype(np.float32)).to(dev)
+    s3 = Bd.System(dims, 2, [1, 1])
+    c3, _ = s3.alloc_coeffs(1, dev)
+    o3 = torch.empty_like(v)
+    ws3 = s3.workspace(1, dev)
+    ms = time_call(lambda: (s3.forward(v, c3, workspace=ws3), s3.inverse(c3, out=o3, workspace=ws3)),
+                   reps)
+    n = s3.R * 128 ** 3
+    out["volume_128"] = {"ms_per_step": round(ms, 4), "coefficients_per_s": n / ms * 1e3,
+                         "R": s3.R, "hbm_algorithmic_GBps": (2 * 4 * n + 8 * 128 ** 3) / ms / 1e6}
+    del v, c3, o3, ws3, s3
+    # 64 images of sizes {256, 384, 512, 1024}^2 (seed 4000), J = 3, levels
+    # [1, 1, 2] (R = 33), FP16 storage, autotuned, one graph replay per step
+    sizes = syn.uneven_sizes(64, 4000)
+    classes = sorted(set(sizes))
+    systems, xs, cs, scs, outs = [], [], [], [], []
+    for nsz in classes:
+        idx = [k for k, z in enumerate(sizes) if z == nsz]
+        img = np.stack([syn.noisy_cartoon2d(nsz, nsz, 4001 + k, 0.1)[1] for k in idx])
+        sy = Bd.System((nsz, nsz), 3, [1, 1, 2], dtype="f16")
+        cc, ss = sy.alloc_coeffs(len(idx), dev)
+        systems.append(sy)
+        xs.append(torch.from_numpy(img.astype(np.float32)).to(dev))
+        cs.append(cc)
+        scs.append(ss)
+        outs.append(torch.empty((len(idx), nsz, nsz), device=dev))
+    m = Bd.Multi(systems, [t.shape[0] for t in xs])
+    wsm = torch.empty(m.workspace_bytes(), dtype=torch.uint8, device=dev)
+    m.autotune(xs, cs, scs, outs, wsm)
+    m.graph_build(3, xs, cs, scs, outs=outs, workspace=wsm)
+    ms = time_call(m.graph_launch, reps)
+    n = sum(sy.R * t.shape[0] * t.shape[1] * t.shape[2] for sy, t in zip(systems, xs))
+    out["uneven_64"] = {"ms_per_step": round(ms, 4), "images_per_s": 64 / ms * 1e3,
+                        "coefficients_per_s": n / ms * 1e3,
+                        "images_per_size": {str(z): sizes.count(z) for z in classes}}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +195,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-other", action="store_true", help="skip the other configurations")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -248,6 +329,9 @@ def main():
         params = np.load(wpath)["params"]
         ev = TR.evaluate(params, size=H, n_scales=J, shear_levels=levels, K=K, n_images=Bn)
         res["learned"] = {k: round(v, 3) for k, v in ev.items()}
+    if not args.no_other:
+        del coeffs, scales, ws
+        res["other_configs"] = other_configs()
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args.cpu_seconds, sig, K, H, W, J, levels)
     print(json.dumps(res))

@@ -55,23 +55,35 @@ struct CTile {
 // ---------------------------------------------------------------------------
 template <int DT>
 struct Store;
+// T is the element type of the coefficient tensor; Raw its bit pattern as a
+// plain scalar (kernels load and store Raw values, so that all loads of a row
+// can be issued before the first conversion).
 template <>
 struct Store<0> {
   using T = float;
+  using Raw = float;
   __device__ static T enc(float v) { return v; }
   __device__ static float dec(T v) { return v; }
+  __device__ static Raw enc_raw(float v) { return v; }
+  __device__ static float dec_raw(Raw v) { return v; }
 };
 template <>
 struct Store<1> {
   using T = __half;
+  using Raw = unsigned short;
   __device__ static T enc(float v) { return __float2half_rn(v); }
   __device__ static float dec(T v) { return __half2float(v); }
+  __device__ static Raw enc_raw(float v) { return __half_as_ushort(__float2half_rn(v)); }
+  __device__ static float dec_raw(Raw v) { return __half2float(__ushort_as_half(v)); }
 };
 template <>
 struct Store<2> {
   using T = __hip_bfloat16;
+  using Raw = unsigned short;
   __device__ static T enc(float v) { return __float2bfloat16(v); }
   __device__ static float dec(T v) { return __bfloat162float(v); }
+  __device__ static Raw enc_raw(float v) { return __bfloat16_as_ushort(__float2bfloat16(v)); }
+  __device__ static float dec_raw(Raw v) { return __uint_as_float((unsigned)v << 16); }
 };
 
 // Coefficient planes are streamed once per call; with SL_NT_COEF the float32
@@ -119,9 +131,21 @@ k_rows_real_fft(const float *__restrict__ x, float2 *__restrict__ A, unsigned *_
     amax = fmaxf(amax, fabsf(a));
   }
   if (xmax) {
-    if (Tile<N>::THREADS % 64 == 0) {
+    if constexpr (Tile<N>::THREADS % 64 == 0) {
+      // one atomic per block: wave maxima through LDS (the FFT's LDS is not
+      // in use yet)
+      constexpr int NWV = Tile<N>::THREADS / 64;
+      float *wm = (float *)lds;
       amax = wave_max(amax);
-      if ((threadIdx.x & 63) == 0) atomicMax(xmax + b, __float_as_uint(amax));
+      if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = amax;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        float mm = wm[0];
+#pragma unroll
+        for (int w = 1; w < NWV; ++w) mm = fmaxf(mm, wm[w]);
+        atomicMax(xmax + b, __float_as_uint(mm));
+      }
+      __syncthreads();
     } else {
       atomicMax(xmax + b, __float_as_uint(amax));   // partial wave: no cross-lane reduction
     }
@@ -235,13 +259,14 @@ k_rows_coef(const float2 *__restrict__ T, typename Store<DT>::T *__restrict__ co
     sa = inv_hw / scales[(size_t)b * R + ia];
     if (ib < R) sb = inv_hw / scales[(size_t)b * R + ib];
   }
-  auto *ca = coef + ((size_t)b * R + ia) * plane + (size_t)row * N;
+  using Raw = typename Store<DT>::Raw;
+  Raw *ca = (Raw *)(coef + ((size_t)b * R + ia) * plane + (size_t)row * N);
 #pragma unroll
-  for (int e = 0; e < E; ++e) coef_store(ca + t + e * NT, Store<DT>::enc(v[e].x * sa));
+  for (int e = 0; e < E; ++e) coef_store(ca + t + e * NT, Store<DT>::enc_raw(v[e].x * sa));
   if (ib < R) {
-    auto *cb = coef + ((size_t)b * R + ib) * plane + (size_t)row * N;
+    Raw *cb = (Raw *)(coef + ((size_t)b * R + ib) * plane + (size_t)row * N);
 #pragma unroll
-    for (int e = 0; e < E; ++e) coef_store(cb + t + e * NT, Store<DT>::enc(v[e].y * sb));
+    for (int e = 0; e < E; ++e) coef_store(cb + t + e * NT, Store<DT>::enc_raw(v[e].y * sb));
   }
 }
 
@@ -303,13 +328,20 @@ k_rows_coef_fft(const typename Store<DT>::T *__restrict__ coef, const float *__r
       if (jb >= 0) db = (thr.K[jb] * sg) * thr.l2[ib];
     }
   }
-  const auto *ca = coef + ((size_t)b * R + ia) * plane + (size_t)rr * N;
-  const auto *cb = coef + ((size_t)b * R + (has_b ? ib : ia)) * plane + (size_t)rr * N;
+  using Raw = typename Store<DT>::Raw;
+  const Raw *ca = (const Raw *)(coef + ((size_t)b * R + ia) * plane + (size_t)rr * N);
+  const Raw *cb = (const Raw *)(coef + ((size_t)b * R + (has_b ? ib : ia)) * plane + (size_t)rr * N);
+  Raw ra[E], rb[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    ra[e] = coef_load(ca + t + e * NT);
+    rb[e] = coef_load(cb + t + e * NT);   // a valid plane; ignored without a partner
+  }
   float2 v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    float a = Store<DT>::dec(coef_load(ca + t + e * NT)) * sa;
-    float bb = has_b ? Store<DT>::dec(coef_load(cb + t + e * NT)) * sb : 0.f;
+    float a = Store<DT>::dec_raw(ra[e]) * sa;
+    float bb = has_b ? Store<DT>::dec_raw(rb[e]) * sb : 0.f;
     if (!(fabsf(a) >= da)) a = 0.f;
     if (!(fabsf(bb) >= db)) bb = 0.f;
     v[e] = make_float2(a, bb);
