@@ -153,11 +153,12 @@ k_conv3x3(const uint16_t *__restrict__ in, const uint16_t *__restrict__ Wp,
 // (k = 2 t + c, k >= 18 zero); layer 2 is the per-tap implicit GEMM.  Layer 3
 // has one output channel: an MFMA with the 9 taps on the M axis yields
 // D[t][p] = sum_ci W3[ci][t] h2[p][ci] for every h2 pixel p, and the output is
-// b3 + sum_t D[t][p + offset(t)].
-// h1 and h2 pixels are padded to 40 channels (80 bytes), which spreads the
-// 16 pixels of an operand read over distinct LDS banks.
+// b3 + sum_t D[t][p + offset(t)].  D needs h2 at p only, so it is computed
+// from the layer-2 accumulators in registers and h2 never reaches LDS.
+// h1 pixels are padded to 40 channels (80 bytes, 16-byte aligned), which
+// spreads the 16 pixels of an operand read over distinct LDS banks.
 // Output tile FTH x 32 (SL_CNN_FTH = 16 or 8), one thread per output pixel;
-// pixel stride of h1 and h2 SL_CNN_CHP bfloat16 values (>= 32).
+// pixel stride of h1 SL_CNN_CHP bfloat16 values (>= 32, a multiple of 8).
 #ifndef SL_CNN_FTH
 #define SL_CNN_FTH 16
 #endif
@@ -171,15 +172,16 @@ constexpr int H2H = FTH + 2, H2W = FTW + 2;
 constexpr int NX0 = X0H * X0W, NH1 = H1H * H1W, NH2 = H2H * H2W;
 constexpr int CHP = SL_CNN_CHP;
 constexpr int kFusedThreads = FTH * FTW;
-static_assert(NH1 % 16 == 0 && CHP % 4 == 0 && CHP >= 32, "tile geometry");
+static_assert(NH1 % 16 == 0 && CHP % 8 == 0 && CHP >= 32, "tile geometry");
 constexpr int kX0PerThread = (NX0 + kFusedThreads - 1) / kFusedThreads;
-// LDS (bytes): h1 | h2 (x0 shares it) | 2 x raw centre coefficients.  The
-// layer-3 partial sums D[16][NH2] reuse the h1 region once layer 2 is done.
-constexpr int kLdsH1 = NH1 * CHP * 2, kLdsH2 = NH2 * CHP * 2, kLdsC = FTH * FTW * 4;
-static_assert(NX0 * 4 <= kLdsH2, "x0 must fit in the h2 region");
-static_assert(16 * NH2 * 4 <= kLdsH1, "layer-3 partial sums must fit in the h1 region");
+// LDS (bytes): h1 | layer-3 partial sums D[16][NH2] | x0 | 2 x raw centre
+// coefficients.  h2 never reaches LDS: layer 3 consumes it from the layer-2
+// accumulators.
+constexpr int kLdsH1 = NH1 * CHP * 2, kLdsD3 = 16 * NH2 * 4, kLdsX0 = ((NX0 * 4 + 15) / 16) * 16,
+              kLdsC = FTH * FTW * 4;
+constexpr int kLdsFused = kLdsH1 + kLdsD3 + kLdsX0 + 2 * kLdsC;
 // blocks of the persistent grid per compute unit (160 KiB of LDS each)
-constexpr int kFusedBlocksPerCU = (2 * (kLdsH1 + kLdsH2 + 2 * kLdsC) <= 160 * 1024) ? 2 : 1;
+constexpr int kFusedBlocksPerCU = (2 * kLdsFused <= 160 * 1024) ? 2 : 1;
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
@@ -224,12 +226,11 @@ k_cnn_fused(const float *__restrict__ coef, CnnPlanes pl, int H, int W, int ntil
             const uint16_t *__restrict__ W1k, const uint16_t *__restrict__ W2p,
             const uint16_t *__restrict__ W3m, const float *__restrict__ params,
             float *__restrict__ coef_out, float *__restrict__ gain) {
-  __shared__ __attribute__((aligned(16))) unsigned char smem[kLdsH1 + kLdsH2 + 2 * kLdsC];
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kLdsFused];
   uint16_t *h1s = (uint16_t *)smem;
-  float *d3 = (float *)smem;                         // layer-3 partials, after layer 2
-  uint16_t *h2s = (uint16_t *)(smem + kLdsH1);
-  uint32_t *x0s = (uint32_t *)(smem + kLdsH1);       // before layer 2
-  float *cs = (float *)(smem + kLdsH1 + kLdsH2);     // [2][FTH * FTW]
+  float *d3 = (float *)(smem + kLdsH1);
+  uint32_t *x0s = (uint32_t *)(smem + kLdsH1 + kLdsD3);
+  float *cs = (float *)(smem + kLdsH1 + kLdsD3 + kLdsX0);   // [2][FTH * FTW]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4;
   constexpr int NW = kFusedThreads / 64;
   const int tiles_x = (W + FTW - 1) / FTW;
@@ -310,25 +311,42 @@ k_cnn_fused(const float *__restrict__ coef, CnnPlanes pl, int H, int W, int ntil
   // inside the image, so no activation needs the zero padding mask
   auto layers = [&](const FusedTile &f, int buf, auto interior) {
     constexpr bool INTERIOR = decltype(interior)::value != 0;
-    // ---- layer 1: NH1 pixels in blocks of 16
-    for (int blk = wave; blk < NH1 / 16; blk += NW) {
-      const int q = blk * 16 + (lane & 15);
-      const int r = q / H1W, c = q % H1W;
-      const int base = r * X0W + c;
-      uint32_t u[4];
+    // ---- layer 1: NH1 pixels in blocks of 16; wave w takes blocks w, w + NW,
+    // ..., two at a time (independent products and operand reads)
+    auto l1 = [&](int bA, auto count) {
+      constexpr int S = decltype(count)::value;
+      bf16x8 xb[S];
+      int qq[S];
 #pragma unroll
-      for (int h = 0; h < 4; ++h) u[h] = x0s[base + toff[h]];
-      const bf16x8 xb = *(const bf16x8 *)u;
-      bool in = true;
-      if constexpr (!INTERIOR) {
-        const int yy = f.ty0 - 2 + r, xx = f.tx0 - 2 + c;
-        in = yy >= 0 && yy < H && xx >= 0 && xx < W;
+      for (int s2 = 0; s2 < S; ++s2) {
+        const int q = (bA + NW * s2) * 16 + (lane & 15);
+        qq[s2] = q;
+        const int base = (q / H1W) * X0W + q % H1W;
+        uint32_t u[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) u[h] = x0s[base + toff[h]];
+        xb[s2] = *(const bf16x8 *)u;
       }
 #pragma unroll
-      for (int nb = 0; nb < 2; ++nb) {
-        const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[nb], xb, bias1[nb], 0, 0, 0);
-        *(bf16x4 *)(h1s + q * CHP + 16 * nb + 4 * g) = relu_bf16x4<INTERIOR>(d, in);
+      for (int s2 = 0; s2 < S; ++s2) {
+        const int q = qq[s2];
+        bool in = true;
+        if constexpr (!INTERIOR) {
+          const int r = q / H1W, c = q % H1W;
+          const int yy = f.ty0 - 2 + r, xx = f.tx0 - 2 + c;
+          in = yy >= 0 && yy < H && xx >= 0 && xx < W;
+        }
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+          const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[nb], xb[s2], bias1[nb], 0, 0, 0);
+          *(bf16x4 *)(h1s + q * CHP + 16 * nb + 4 * g) = relu_bf16x4<INTERIOR>(d, in);
+        }
       }
+    };
+    constexpr int NB1 = NH1 / 16;
+    for (int bA = wave; bA < NB1; bA += 2 * NW) {
+      if (bA + NW < NB1) l1(bA, IntC<2>{});
+      else l1(bA, IntC<1>{});
     }
     __syncthreads();
     // ---- layer 2: NH2 pixels in NB2 blocks of 16 (the last may be partial).
@@ -372,38 +390,33 @@ k_cnn_fused(const float *__restrict__ coef, CnnPlanes pl, int H, int W, int ntil
           for (int s = 0; s < S; ++s) xa[s] = xn[s];
         }
       }
+      // layer 3 on the h2 values of these pixels: lane group g holds channels
+      // 4 g .. 4 g + 3 and 16 + 4 g .. 16 + 4 g + 3 of its pixel, the K order
+      // of the packed layer-3 weights; D[t][q] for the 16 taps (9 used)
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         const int q = qq[s];
-        if (q >= NH2) continue;
         bool in = true;
         if constexpr (!INTERIOR) {
-          const int r = q / H2W, c = q % H2W;
+          const int qc = q < NH2 ? q : NH2 - 1;
+          const int r = qc / H2W, c = qc % H2W;
           const int yy = f.ty0 - 1 + r, xx = f.tx0 - 1 + c;
           in = yy >= 0 && yy < H && xx >= 0 && xx < W;
         }
+        const bf16x4 lo = relu_bf16x4<INTERIOR>(acc[s][0], in);
+        const bf16x4 hi = relu_bf16x4<INTERIOR>(acc[s][1], in);
+        const bf16x8 hb = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+        const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3, hb, f32x4{0.f, 0.f, 0.f, 0.f},
+                                                                0, 0, 0);
+        if (q < NH2) {
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
-          *(bf16x4 *)(h2s + q * CHP + 16 * nb + 4 * g) = relu_bf16x4<INTERIOR>(acc[s][nb], in);
+          for (int e = 0; e < 4; ++e) d3[(4 * g + e) * NH2 + q] = d[e];
+        }
       }
     };
     for (int bA = wave; bA < NB2; bA += 2 * NW) {
       if (bA + NW < NB2) l2(bA, IntC<2>{});
       else l2(bA, IntC<1>{});
-    }
-    __syncthreads();
-    // ---- layer 3, per-tap partial sums over the 32 channels of every h2 pixel;
-    // taps 9..15 have zero weights and land in unused rows of d3
-    for (int blk = wave; blk < NB2; blk += NW) {
-      const int q = blk * 16 + (lane & 15);
-      const int qc = q < NH2 ? q : NH2 - 1;
-      const bf16x8 xb = *(const bf16x8 *)(h2s + qc * CHP + 8 * g);
-      const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3, xb, f32x4{0.f, 0.f, 0.f, 0.f},
-                                                              0, 0, 0);
-      if (q < NH2) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) d3[(4 * g + e) * NH2 + q] = d[e];
-      }
     }
     __syncthreads();
     // ---- output: one pixel per thread
@@ -443,7 +456,8 @@ k_cnn_fused(const float *__restrict__ coef, CnnPlanes pl, int H, int W, int ntil
     if (interior) layers(f, buf, IntC<1>{});
     else layers(f, buf, IntC<0>{});
     if (next >= ntiles) break;
-    // h2 reads ended at the last barrier: stage the next tile into x0 / cs
+    // x0 was last read by layer 1 and the other centre buffer by the previous
+    // tile's output: stage the next tile
     buf ^= 1;
     stage(fn, buf);
     tile = next;
@@ -586,8 +600,12 @@ __global__ void k_pack(const float *__restrict__ params, int J, int layer, int m
     const int tt = k >> 1, cc = k & 1;
     if (n < 32 && tt < 9) v = P[off[0] + (n * 2 + cc) * 9 + tt];
   } else if (mode == 3) {
-    // layer 3 with the taps as output rows: row n = tap, column k = channel
-    if (n < 9) v = P[off[2] + k * 9 + n];
+    // layer 3 with the taps as output rows: row n = tap.  Column k of lane
+    // group kg = k / 8 is the channel that the layer-2 accumulators of that
+    // group hold: 4 kg + k % 8 for k % 8 < 4, else 16 + 4 kg + k % 8 - 4.
+    const int kg = k >> 3, kj = k & 7;
+    const int ch = kj < 4 ? 4 * kg + kj : 16 + 4 * kg + (kj - 4);
+    if (n < 9) v = P[off[2] + ch * 9 + n];
   } else if (mode == 0) {
     if (n < cout[l] && k < cin[l]) v = P[off[l] + (n * cin[l] + k) * 9 + t];
   } else {
