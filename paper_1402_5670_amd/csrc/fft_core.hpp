@@ -162,9 +162,17 @@ __device__ __forceinline__ void line_sync() {
 template <int NT>
 constexpr bool wave_lines() { return NT <= 64 && 64 % NT == 0; }
 
-template <class PL, int S_, bool INV, bool WAVE = false>
-__device__ __forceinline__ void fft_stage(float2 (&v)[PL::E], int t, const LdsLine &lds,
-                                          const float2 *__restrict__ tw) {
+// Twiddle tables: a global table (read through the scalar-uniform pointer) or
+// a copy staged in LDS by the calling kernel (TwLds), whose reads are not
+// hoisted out of a caller's loop into registers.
+struct TwLds {
+  const float2 *p;
+};
+__device__ __forceinline__ float2 tw_at(const float2 *__restrict__ tw, int i) { return tw[i]; }
+__device__ __forceinline__ float2 tw_at(TwLds tw, int i) { return tw.p[i]; }
+
+template <class PL, int S_, bool INV, bool WAVE = false, class TW = const float2 *>
+__device__ __forceinline__ void fft_stage(float2 (&v)[PL::E], int t, const LdsLine &lds, TW tw) {
   constexpr int N = PL::N;
   constexpr int E = PL::E, NT = PL::NT;
   constexpr int r = PL::radix(S_);
@@ -193,7 +201,7 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[PL::E], int t, const LdsLi
       int k = i % p;
 #pragma unroll
       for (int q = 1; q < r; ++q) {
-        float2 w = tw[q * k * (N / (p * r))];
+        float2 w = tw_at(tw, q * k * (N / (p * r)));
         x[b][q] = INV ? cmulconj(x[b][q], w) : cmul(x[b][q], w);
       }
     }
@@ -217,23 +225,21 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[PL::E], int t, const LdsLi
   }
 }
 
-template <class PL, bool INV, bool WAVE, int S_ = 0>
-__device__ __forceinline__ void fft_stages(float2 (&v)[PL::E], int t, const LdsLine &lds,
-                                           const float2 *__restrict__ tw) {
+template <class PL, bool INV, bool WAVE, int S_ = 0, class TW>
+__device__ __forceinline__ void fft_stages(float2 (&v)[PL::E], int t, const LdsLine &lds, TW tw) {
   if constexpr (S_ < PL::S) {
-    fft_stage<PL, S_, INV, WAVE>(v, t, lds, tw);
-    fft_stages<PL, INV, WAVE, S_ + 1>(v, t, lds, tw);
+    fft_stage<PL, S_, INV, WAVE, TW>(v, t, lds, tw);
+    fft_stages<PL, INV, WAVE, S_ + 1, TW>(v, t, lds, tw);
   }
 }
 
 // Full length-N FFT of one line held in registers (see file comment).  The
 // leading barrier makes it safe to call repeatedly on the same LDS buffer.
 // A single-stage plan never touches LDS.
-template <class PL, bool INV, bool WAVE = false>
-__device__ __forceinline__ void fft_line_p(float2 (&v)[PL::E], int t, const LdsLine &lds,
-                                           const float2 *__restrict__ tw) {
+template <class PL, bool INV, bool WAVE = false, class TW = const float2 *>
+__device__ __forceinline__ void fft_line_p(float2 (&v)[PL::E], int t, const LdsLine &lds, TW tw) {
   if constexpr (PL::S > 1) line_sync<WAVE>();
-  fft_stages<PL, INV, WAVE>(v, t, lds, tw);
+  fft_stages<PL, INV, WAVE, 0, TW>(v, t, lds, tw);
 }
 
 // Row lines (one line per NT consecutive threads): wavefront-local exchanges
