@@ -120,3 +120,23 @@ def test_error_codes():
     assert _lib().sl_config_num_subbands(ctypes.byref(cfg), ctypes.byref(R)) == -1
     assert b"ndim" in _lib().sl_last_error()
     assert _lib().sl_config_num_subbands(None, ctypes.byref(R)) == -1
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    # the product path has no fallback: without the built library every entry
+    # point raises instead of computing anything elsewhere
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1402_5670_amd import binding as B\n"
+            "try:\n"
+            "    B.lib()\n"
+            "except ImportError as e:\n"
+            "    print('raised', e)\n"
+            "    sys.exit(0)\n"
+            "sys.exit(3)\n") % ROOT
+    env = dict(os.environ, SL_LIB=str(tmp_path / "absent.so"))
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "raised" in r.stdout
