@@ -77,8 +77,10 @@ def measured_traffic(pass_name):
         t = json.load(fh)
     if t.get("source_hash") != profiling.source_hash():
         return None
+    import re
     for k, v in t["kernels"].items():
-        if f"k_{pass_name}<" in k:
+        # kernel variants carry a digit after the pass name (k_cols_filter_ifft3<...>)
+        if re.search(rf"k_{pass_name}\d*<", k):
             return {"read_bytes": v["read_bytes"], "write_bytes": v["write_bytes"],
                     "bytes": v["read_bytes"] + v["write_bytes"], "kernel": k}
     return None
