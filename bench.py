@@ -126,7 +126,8 @@ def time_call(fn, reps):
 def other_configs(reps=10):
     """The other hot-path configurations, timed on the same GPU (not the
     headline): FP16 coefficient storage on the 32 x 512^2 batch, the 128^3
-    volume, and the uneven batch of 64 images replayed from its HIP graph."""
+    volume, a 192^3 video volume with R = 292, and the uneven batch of 64
+    images replayed from its HIP graph."""
     import numpy as np
     import torch
     from paper_1402_5670_amd import binding as Bd
@@ -162,6 +163,24 @@ def other_configs(reps=10):
     out["volume_128"] = {"ms_per_step": round(ms, 4), "coefficients_per_s": n / ms * 1e3,
                          "R": s3.R, "hbm_algorithmic_GBps": (2 * 4 * n + 8 * 128 ** 3) / ms / 1e6}
     del v, c3, o3, ws3, s3
+    # 192^3 video volume, J = 3, levels [1, 1, 2] (R = 292), forward + inverse
+    dims = (192, 192, 192)
+    v = torch.from_numpy((syn.moving_ellipses_video(*dims, 5000) +
+                          syn.noise(dims, 5000, 0.1))[None].astype(np.float32)).to(dev)
+    t0 = time.perf_counter()
+    s3 = Bd.System(dims, 3, [1, 1, 2])
+    build_s = time.perf_counter() - t0
+    c3, _ = s3.alloc_coeffs(1, dev)
+    o3 = torch.empty_like(v)
+    ws3 = s3.workspace(1, dev)
+    ms = time_call(lambda: (s3.forward(v, c3, workspace=ws3), s3.inverse(c3, out=o3, workspace=ws3)),
+                   max(2, reps // 2))
+    n = s3.R * 192 ** 3
+    out["video_192"] = {"ms_per_step": round(ms, 4), "coefficients_per_s": n / ms * 1e3,
+                        "R": s3.R, "hbm_algorithmic_GBps": (2 * 4 * n + 8 * 192 ** 3) / ms / 1e6,
+                        "system_build_s": round(build_s, 1)}
+    del v, c3, o3, ws3, s3
+    torch.cuda.empty_cache()
     # 64 images of sizes {256, 384, 512, 1024}^2 (seed 4000), J = 3, levels
     # [1, 1, 2] (R = 33), FP16 storage, autotuned, one graph replay per step
     sizes = syn.uneven_sizes(64, 4000)

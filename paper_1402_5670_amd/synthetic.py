@@ -124,6 +124,31 @@ def cartoon3d(D, H, W, seed):
     return vol
 
 
+def moving_ellipses_video(T, H, W, seed):
+    """T frames of H x W (a [T][H][W] volume): background U[0,1] and 6-12
+    ellipses of intensity U[0,1] that translate at constant velocity and
+    rotate at a constant rate over the frames (painter's order, membership at
+    pixel centres), a synthetic stand-in for video data."""
+    rng = np.random.default_rng(seed)
+    vol = np.full((T, H, W), rng.uniform(0.0, 1.0))
+    yy, xx = np.meshgrid(np.arange(H) + 0.5, np.arange(W) + 0.5, indexing="ij")
+    m = float(min(H, W))
+    for _ in range(int(rng.integers(6, 13))):
+        val = rng.uniform(0.0, 1.0)
+        c0 = rng.uniform([0, 0], [H, W])
+        vel = rng.uniform(-0.5, 0.5, size=2)            # pixels per frame
+        a, b = rng.uniform(m / 24, m / 5, size=2)
+        th0, om = rng.uniform(0.0, np.pi), rng.uniform(-0.02, 0.02)
+        for t in range(T):
+            cy, cx = c0 + vel * t
+            th = th0 + om * t
+            u = (xx - cx) * np.cos(th) + (yy - cy) * np.sin(th)
+            v = -(xx - cx) * np.sin(th) + (yy - cy) * np.cos(th)
+            mask = (u / a) ** 2 + (v / b) ** 2 <= 1.0
+            vol[t][mask] = val
+    return vol
+
+
 def noise(shape, seed, sigma):
     return np.random.default_rng([seed, 1]).standard_normal(shape) * sigma
 

@@ -116,3 +116,37 @@ def test_3d_denoise_fused_matches():
     got = s32.denoise_fused(xg, sig, K)
     torch.cuda.synchronize()
     assert rel(got.cpu().numpy(), ref.cpu().numpy()) < 1e-6
+
+
+def test_video_192_three_scales():
+    # 192^3 video volume (moving ellipses), 3 scales, shear levels [1, 1, 2]
+    # (R = 292, Sec. 4.4): sampled subbands against the oracle, normalised by
+    # ||x|| rms(psi_hat_i); perfect reconstruction of the whole volume; hard
+    # thresholding with K = [3, 3, 4] improves the PSNR
+    print("case: 192^3 video J=3 d=[1,1,2] R=292", flush=True)
+    dims = (192, 192, 192)
+    clean = syn.moving_ellipses_video(*dims, 5000)
+    x = clean + syn.noise(dims, 5000, 0.1)
+    s = B.System(dims, 3, [1, 1, 2])
+    assert s.R == 292
+    xg = _gpu(x[None])
+    c, _ = s.forward(xg)
+    xr = s.inverse(c)
+    torch.cuda.synchronize()
+    assert rel(xr.cpu().numpy()[0], x) < 1e-5
+    want = {0, 1, 40, 97, 150, 200, 291}
+    X = np.fft.fftn(x)
+    nx = np.linalg.norm(x)
+    worst = 0.0
+    for i, (sb, hat) in enumerate(S.iter_filters_3d(dims, 3, [1, 1, 2])):
+        if i not in want:
+            continue
+        ref = np.fft.ifftn(X * hat).real
+        got = c[0, i].cpu().numpy().astype(np.float64)
+        worst = max(worst, np.linalg.norm(got - ref) / (nx * np.sqrt(np.mean(hat ** 2))))
+    print(f"worst normalised subband error {worst:.2e}", flush=True)
+    assert worst < 1e-5
+    sig = _gpu(np.array([0.1], dtype=np.float32))
+    out = s.denoise(xg, sig, [3.0, 3.0, 4.0], coeffs=c)
+    torch.cuda.synchronize()
+    assert T.psnr(clean, out.cpu().numpy()[0]) > T.psnr(clean, x) + 3.0
