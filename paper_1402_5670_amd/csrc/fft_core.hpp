@@ -95,7 +95,10 @@ __device__ __forceinline__ void dft_r(float2 *x) {
 }
 
 // ---------------------------------------------------------------------------
-// compile-time radix plans: 8s first, then a 4 or 2, then 3s
+// compile-time radix plans.  Powers of two: 8s first, then a 4 or a 2.
+// Lengths with a factor 3: 4s first, then a 2, then 3s, so that a thread holds
+// lcm(4, 3) = 12 values (radix-8 stages would make it lcm(8, 3) = 24 and
+// double the registers per thread).
 // ---------------------------------------------------------------------------
 template <int N_, int EMUL = 1>
 struct Plan {
@@ -103,12 +106,13 @@ struct Plan {
   static constexpr int count3() { int n = N, c = 0; while (n % 3 == 0) { n /= 3; ++c; } return c; }
   static constexpr int pow2() { int n = N; while (n % 3 == 0) n /= 3; return n; }
   static constexpr int log2p() { int n = pow2(), c = 0; while (n > 1) { n /= 2; ++c; } return c; }
-  static constexpr int n8 = log2p() / 3;
-  static constexpr int rem2 = log2p() % 3;              // 0, 1 (radix 2) or 2 (radix 4)
   static constexpr int n3 = count3();
-  static constexpr int S = n8 + (rem2 ? 1 : 0) + n3;
+  static constexpr int hi = n3 ? 4 : 8;                          // leading radix
+  static constexpr int nhi = n3 ? log2p() / 2 : log2p() / 3;     // its stage count
+  static constexpr int rem2 = n3 ? log2p() % 2 : log2p() % 3;    // 0, 1 (radix 2) or 2 (radix 4)
+  static constexpr int S = nhi + (rem2 ? 1 : 0) + n3;
   static constexpr int radix(int s) {
-    return s < n8 ? 8 : (rem2 && s == n8) ? (rem2 == 1 ? 2 : 4) : 3;
+    return s < nhi ? hi : (rem2 && s == nhi) ? (rem2 == 1 ? 2 : 4) : 3;
   }
   static constexpr int lcm_radix() {
     int l = 1;

@@ -23,14 +23,53 @@ struct Tile3 {
   static constexpr int THREADS = M * NT;
 };
 
-// psi_hat_i at voxel (z, y, x)
-__device__ __forceinline__ float filter3d(const Sub3D &d, const float *__restrict__ tab, int z,
-                                          int y, int x) {
-  const int idx[4] = {0, x, y, z};
-  if (d.cone == 0) return tab[d.g_off + x] * tab[d.p1_off + y] * tab[d.p2_off + z];
+// psi_hat_i along the z line of voxel column (y, x).  Unless z is the
+// pyramid's main axis, only one factor varies along the line:
+//   psi_hat(z) = c * tab[base + z * stride],
+// with c the product of the two factors that are constant on the line (the
+// lowpass: g_hat(x) h_hat(y) times h_hat(z)).  With z as the main axis all
+// three factors vary: psi_hat(z) = tab[g + z] * tab[p1 + z] * tab[p2 + z].
+struct ZLine {
+  float c;
+  int base, stride;   // one varying factor (main axis x or y, or lowpass)
+  int g, p1, p2;      // main axis z (stride < 0 marks this case)
+};
+
+__device__ __forceinline__ ZLine zline(const Sub3D &d, const float *__restrict__ tab, int y,
+                                       int x) {
+  ZLine L;
+  L.g = L.p1 = L.p2 = 0;
+  if (d.cone == 0) {
+    L.c = tab[d.g_off + x] * tab[d.p1_off + y];
+    L.base = d.p2_off;
+    L.stride = 1;
+    return L;
+  }
+  const int idx[4] = {0, x, y, 0};
+  if (d.am == 3) {
+    L.c = 1.f;
+    L.base = 0;
+    L.stride = -1;
+    L.g = d.g_off;
+    L.p1 = d.p1_off + idx[d.s1] * d.n_main;
+    L.p2 = d.p2_off + idx[d.s2] * d.n_main;
+    return L;
+  }
   const int im = idx[d.am];
-  return tab[d.g_off + im] * tab[d.p1_off + idx[d.s1] * d.n_main + im] *
-         tab[d.p2_off + idx[d.s2] * d.n_main + im];
+  if (d.s1 == 3) {
+    L.c = tab[d.g_off + im] * tab[d.p2_off + idx[d.s2] * d.n_main + im];
+    L.base = d.p1_off + im;
+  } else {
+    L.c = tab[d.g_off + im] * tab[d.p1_off + idx[d.s1] * d.n_main + im];
+    L.base = d.p2_off + im;
+  }
+  L.stride = d.n_main;
+  return L;
+}
+
+__device__ __forceinline__ float zline_at(const ZLine &L, const float *__restrict__ tab, int z) {
+  if (L.stride >= 0) return L.c * tab[L.base + z * L.stride];
+  return tab[L.g + z] * tab[L.p1 + z] * tab[L.p2 + z];
 }
 
 // z pass of the forward transform: F * (psi_a + i psi_b), inverse DFT along z.
@@ -55,14 +94,14 @@ k_z_filter_ifft(const float2 *__restrict__ F, const Sub3D *__restrict__ subs,
   for (int e = 0; e < E; ++e) f[e] = F[(size_t)b * vol + (size_t)(t + e * NT) * HW + cc];
   for (int pp = 0; pp < np; ++pp) {
     const int ia = 2 * (p0 + pp), ib = ia + 1;
-    const Sub3D da = subs[ia];
-    const Sub3D db = subs[ib < R ? ib : ia];
+    const ZLine la = zline(subs[ia], tab, y, x);
+    const ZLine lb = zline(subs[ib < R ? ib : ia], tab, y, x);
     float2 v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int z = t + e * NT;
-      const float a = filter3d(da, tab, z, y, x);
-      const float bb = ib < R ? filter3d(db, tab, z, y, x) : 0.f;
+      const float a = zline_at(la, tab, z);
+      const float bb = ib < R ? zline_at(lb, tab, z) : 0.f;
       v[e] = make_float2(f[e].x * a - f[e].y * bb, f[e].y * a + f[e].x * bb);
     }
     fft_line_p<Plan<N>, true>(v, t, LdsLine{lds + m, M}, tw);
@@ -105,13 +144,13 @@ k_z_fft_acc(const float2 *__restrict__ U, const Sub3D *__restrict__ subs,
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = Ui[(size_t)(t + e * NT) * HW];
     fft_line_p<Plan<N>, false>(v, t, LdsLine{lds + m, M}, tw);
-    const Sub3D da = subs[ia];
-    const Sub3D db = subs[ib < R ? ib : ia];
+    const ZLine la = zline(subs[ia], tab, y, x);
+    const ZLine lb = zline(subs[ib < R ? ib : ia], tab, y, x);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int z = t + e * NT;
-      const float a = filter3d(da, tab, z, y, x);
-      const float bb = ib < R ? filter3d(db, tab, z, y, x) : 0.f;
+      const float a = zline_at(la, tab, z);
+      const float bb = ib < R ? zline_at(lb, tab, z) : 0.f;
       acc[e].x += a * v[e].x + bb * v[e].y;
       acc[e].y += a * v[e].y - bb * v[e].x;
     }
