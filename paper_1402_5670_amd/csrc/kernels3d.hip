@@ -81,6 +81,8 @@ k_z_filter_ifft(const float2 *__restrict__ F, const Sub3D *__restrict__ subs,
                 int b0, int p0, int np, const float2 *__restrict__ tw) {
   constexpr int NT = Tile3<N>::NT, M = Tile3<N>::M, E = Tile3<N>::E;
   __shared__ float2 lds[M * N];
+  __shared__ float2 twl[N];   // twiddles staged once (ordered by the FFT's leading barrier)
+  for (int i = threadIdx.x; i < N; i += blockDim.x) twl[i] = tw[i];
   const int HW = H * W;
   const int m = threadIdx.x % M, t = threadIdx.x / M;
   const int col = blockIdx.x * M + m;
@@ -104,7 +106,7 @@ k_z_filter_ifft(const float2 *__restrict__ F, const Sub3D *__restrict__ subs,
       const float bb = ib < R ? zline_at(lb, tab, z) : 0.f;
       v[e] = make_float2(f[e].x * a - f[e].y * bb, f[e].y * a + f[e].x * bb);
     }
-    fft_line_p<Plan<N>, true>(v, t, LdsLine{lds + m, M}, tw);
+    fft_line_p<Plan<N>, true>(v, t, LdsLine{lds + m, M}, TwLds{twl});
     if (ok) {
       float2 *To = T + ((size_t)blockIdx.y * np + pp) * vol + col;
 #pragma unroll
@@ -124,6 +126,8 @@ k_z_fft_acc(const float2 *__restrict__ U, const Sub3D *__restrict__ subs,
             const float2 *__restrict__ tw) {
   constexpr int NT = Tile3<N>::NT, M = Tile3<N>::M, E = Tile3<N>::E;
   __shared__ float2 lds[M * N];
+  __shared__ float2 twl[N];   // twiddles staged once (ordered by the FFT's leading barrier)
+  for (int i = threadIdx.x; i < N; i += blockDim.x) twl[i] = tw[i];
   const int HW = H * W;
   const int m = threadIdx.x % M, t = threadIdx.x / M;
   const int col = blockIdx.x * M + m;
@@ -143,7 +147,7 @@ k_z_fft_acc(const float2 *__restrict__ U, const Sub3D *__restrict__ subs,
     float2 v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = Ui[(size_t)(t + e * NT) * HW];
-    fft_line_p<Plan<N>, false>(v, t, LdsLine{lds + m, M}, tw);
+    fft_line_p<Plan<N>, false>(v, t, LdsLine{lds + m, M}, TwLds{twl});
     const ZLine la = zline(subs[ia], tab, y, x);
     const ZLine lb = zline(subs[ib < R ? ib : ia], tab, y, x);
 #pragma unroll
@@ -162,7 +166,7 @@ k_z_fft_acc(const float2 *__restrict__ U, const Sub3D *__restrict__ subs,
       const float d = ps[(size_t)(t + e * NT) * HW];
       acc[e] = make_float2(acc[e].x / d, acc[e].y / d);
     }
-    fft_line_p<Plan<N>, true>(acc, t, LdsLine{lds + m, M}, tw);
+    fft_line_p<Plan<N>, true>(acc, t, LdsLine{lds + m, M}, TwLds{twl});
   }
   if (ok) {
 #pragma unroll
