@@ -495,73 +495,127 @@ __global__ void k_cnn_dz(const float *__restrict__ dcoef, const float *__restric
 // db[co] = sum_p dy[p][co] over the tiles of planes of one scale.  Each block
 // walks tiles with a grid stride and writes one partial [9*32*32 + 32].
 // Pixels are the reduction axis: A[m = ci][k = pixel], B[k = pixel][n = co].
+// Weight gradients of one layer over a range of planes: for every tap t,
+// dW[t][ci][co] = sum_p x[p + offset(t)][ci] dy[p][co] (implicit GEMM with the
+// pixels on the reduction axis; operands transposed to channel-major tiles in
+// LDS) and dbias[co] = sum_p dy[p][co].  MB x NB selects the 16 x 16 blocks of
+// (ci, co) that can be nonzero: layer 1 has 2 input channels (MB = 1), layer 3
+// one output channel (NB = 1).  Only the channel quarters that those blocks
+// read are loaded (XQ, DQ quarters of 8 channels).  A wave takes one tap row
+// dy and one (mb, nb) block and computes its three taps dx = 0, 1, 2 together:
+// the x rows are padded to 16-byte alignment, each lane reads 16 pixels with
+// two aligned 16-byte loads and forms the three shifted operands in registers,
+// and the dy operand is shared.  Each block writes its partial sums;
+// k_reduce_partials adds them in a fixed order.
+constexpr int kWgRow = 48;   // padded halo row (>= TW + 2 + 14, multiple of 8)
+template <int MB, int NB>
 __global__ void __launch_bounds__(256)
 k_conv_wgrad(const uint16_t *__restrict__ x, const uint16_t *__restrict__ dy, int H, int W,
              int plane0, int nplanes, float *__restrict__ partial) {
-  __shared__ __attribute__((aligned(16))) uint16_t xs[CH][HH * HW2 + 8];
-  __shared__ __attribute__((aligned(16))) uint16_t ds[CH][TH * TW];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int XQ = 2 * MB, DQ = 2 * NB;            // channel quarters of x and dy
+  constexpr int NTRIP = 3 * MB * NB;                  // (tap row, mb, nb) units
+  constexpr int TPW = (NTRIP + 3) / 4;                // per wave (4 waves)
+  __shared__ __attribute__((aligned(16))) uint16_t xs[8 * XQ][HH * kWgRow];
+  __shared__ __attribute__((aligned(16))) uint16_t ds[8 * DQ][TH * TW];
+  __shared__ float bsum[256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4;
   const size_t HWn = (size_t)H * W;
-  // wave w owns (tap, mb, nb) triples w, w + 4, ..., 36 in all
-  f32x4 acc[9];
+  f32x4 acc[TPW][3];
 #pragma unroll
-  for (int s = 0; s < 9; ++s) acc[s] = f32x4{0.f, 0.f, 0.f, 0.f};
-  float dbias = 0.f;
+  for (int s = 0; s < TPW; ++s)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) acc[s][d] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float dbias = 0.f;     // channel threadIdx.x % 32, pixels threadIdx.x / 32 + 8 i
   const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + TH - 1) / TH;
   const int ntiles = nplanes * tiles_x * tiles_y;
   for (int q = blockIdx.x; q < ntiles; q += gridDim.x) {
-    const int tid = q;
-    const int p = plane0 + tid / (tiles_x * tiles_y);
-    const int rem = tid % (tiles_x * tiles_y);
+    const int p = plane0 + q / (tiles_x * tiles_y);
+    const int rem = q % (tiles_x * tiles_y);
     const int ty0 = (rem / tiles_x) * TH, tx0 = (rem % tiles_x) * TW;
     __syncthreads();
-    for (int k = threadIdx.x; k < HH * HW2; k += 256) {
-      const int yy = ty0 + k / HW2 - 1, xx = tx0 + k % HW2 - 1;
-      const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
-      const uint16_t *s = x + ((size_t)p * HWn + (in ? (size_t)yy * W + xx : 0)) * CH;
+    // halo tile of x and output tile of dy, 8 channels (16 bytes) per load,
+    // transposed to [channel][pixel]
+    for (int k = threadIdx.x; k < HH * HW2 * XQ; k += 256) {
+      const int pix = k / XQ, qu = k % XQ;
+      const int r = pix / HW2, c = pix % HW2;
+      const int yy = ty0 + r - 1, xx = tx0 + c - 1;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+        v = ((const uint4 *)(x + ((size_t)p * HWn + (size_t)yy * W + xx) * CH))[qu];
+      const uint16_t *h = (const uint16_t *)&v;
 #pragma unroll
-      for (int c = 0; c < CH; ++c) xs[c][k] = in ? s[c] : (uint16_t)0;
+      for (int e = 0; e < 8; ++e) xs[8 * qu + e][r * kWgRow + c] = h[e];
     }
-    for (int k = threadIdx.x; k < TH * TW; k += 256) {
-      const int yy = ty0 + k / TW, xx = tx0 + k % TW;
-      const bool in = yy < H && xx < W;
-      const uint16_t *s = dy + ((size_t)p * HWn + (in ? (size_t)yy * W + xx : 0)) * CH;
+    for (int k = threadIdx.x; k < TH * TW * DQ; k += 256) {
+      const int pix = k / DQ, qu = k % DQ;
+      const int yy = ty0 + pix / TW, xx = tx0 + pix % TW;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (yy < H && xx < W)
+        v = ((const uint4 *)(dy + ((size_t)p * HWn + (size_t)yy * W + xx) * CH))[qu];
+      const uint16_t *h = (const uint16_t *)&v;
 #pragma unroll
-      for (int c = 0; c < CH; ++c) ds[c][k] = in ? s[c] : (uint16_t)0;
+      for (int e = 0; e < 8; ++e) ds[8 * qu + e][pix] = h[e];
     }
     __syncthreads();
-    if (threadIdx.x < CH)
-      for (int k = 0; k < TH * TW; ++k) dbias += bf2f(ds[threadIdx.x][k]);
+    if ((threadIdx.x & 31) < 8 * DQ) {
+      const int c = threadIdx.x & 31;
 #pragma unroll
-    for (int s = 0; s < 9; ++s) {
-      const int trip = wave + 4 * s;          // 0..35
-      const int t = trip >> 2, mb = (trip >> 1) & 1, nb = trip & 1;
-      const int dyy = t / 3, dxx = t % 3;
-      const int ci = 16 * mb + (lane & 15), co = 16 * nb + (lane & 15);
-      for (int r = 0; r < TH; ++r) {
-        uint16_t av[8];
-        const uint16_t *xa = &xs[ci][(r + dyy) * HW2 + dxx + 8 * (lane >> 4)];
+      for (int k = threadIdx.x >> 5; k < TH * TW; k += 8) dbias += bf2f(ds[c][k]);
+    }
 #pragma unroll
-        for (int e = 0; e < 8; ++e) av[e] = xa[e];
-        const bf16x8 a = *(const bf16x8 *)av;
-        const bf16x8 bb = *(const bf16x8 *)&ds[co][r * TW + 8 * (lane >> 4)];
-        acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc[s], 0, 0, 0);
+    for (int s = 0; s < TPW; ++s) {
+      const int trip = wave + 4 * s;
+      if (trip < NTRIP) {
+        const int dyy = trip / (MB * NB), mb = (trip / NB) % MB, nb = trip % NB;
+        const int ci = 16 * mb + (lane & 15), co = 16 * nb + (lane & 15);
+        for (int r = 0; r < TH; ++r) {
+          const uint4 u0 = *(const uint4 *)&xs[ci][(r + dyy) * kWgRow + 8 * g];
+          const uint4 u1 = *(const uint4 *)&xs[ci][(r + dyy) * kWgRow + 8 * g + 8];
+          const bf16x8 bb = *(const bf16x8 *)&ds[co][r * TW + 8 * g];
+          // pixels 8 g + dx .. 8 g + dx + 7 of the halo row for dx = 0, 1, 2
+          const uint4 a1 = make_uint4(__builtin_amdgcn_alignbit(u0.y, u0.x, 16),
+                                      __builtin_amdgcn_alignbit(u0.z, u0.y, 16),
+                                      __builtin_amdgcn_alignbit(u0.w, u0.z, 16),
+                                      __builtin_amdgcn_alignbit(u1.x, u0.w, 16));
+          const uint4 a2 = make_uint4(u0.y, u0.z, u0.w, u1.x);
+          acc[s][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*(const bf16x8 *)&u0, bb, acc[s][0], 0, 0, 0);
+          acc[s][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*(const bf16x8 *)&a1, bb, acc[s][1], 0, 0, 0);
+          acc[s][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*(const bf16x8 *)&a2, bb, acc[s][2], 0, 0, 0);
+        }
       }
     }
   }
-  // D[m = ci][n = co]: lane holds ci = 16 mb + 4 (lane / 16) + e, co = 16 nb + lane % 16
+  // D[m = ci][n = co]: lane holds ci = 16 mb + 4 (lane / 16) + e, co = 16 nb + lane % 16;
+  // blocks outside MB x NB are zero
   float *dst = partial + (size_t)blockIdx.x * (9 * CH * CH + CH);
+  for (int k = threadIdx.x; k < 9 * CH * CH; k += 256) {
+    const int ci = (k / CH) % CH, co = k % CH;
+    if (ci >= 16 * MB || co >= 16 * NB) dst[k] = 0.f;
+  }
 #pragma unroll
-  for (int s = 0; s < 9; ++s) {
+  for (int s = 0; s < TPW; ++s) {
     const int trip = wave + 4 * s;
-    const int t = trip >> 2, mb = (trip >> 1) & 1, nb = trip & 1;
+    if (trip < NTRIP) {
+      const int dyy = trip / (MB * NB), mb = (trip / NB) % MB, nb = trip % NB;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int ci = 16 * mb + 4 * (lane >> 4) + e, co = 16 * nb + (lane & 15);
-      dst[(t * CH + ci) * CH + co] = acc[s][e];
+      for (int d = 0; d < 3; ++d) {
+        const int t = 3 * dyy + d;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int ci = 16 * mb + 4 * g + e, co = 16 * nb + (lane & 15);
+          dst[(t * CH + ci) * CH + co] = acc[s][d][e];
+        }
+      }
     }
   }
-  if (threadIdx.x < CH) dst[9 * CH * CH + threadIdx.x] = dbias;
+  bsum[threadIdx.x] = dbias;
+  __syncthreads();
+  if (threadIdx.x < CH) {
+    float sum = 0.f;
+#pragma unroll
+    for (int g2 = 0; g2 < 8; ++g2) sum += bsum[g2 * 32 + threadIdx.x];
+    dst[9 * CH * CH + threadIdx.x] = sum;
+  }
 }
 
 // Sum block partials in a fixed order (deterministic).
@@ -680,9 +734,19 @@ hipError_t cnn_dz(const float *dcoef, const float *coef, const float *gain, cons
 }
 
 hipError_t cnn_wgrad(const uint16_t *x, const uint16_t *dy, int H, int W, int plane0,
-                     int nplanes, int nblocks, float *partial, float *outv, hipStream_t st) {
-  hipLaunchKernelGGL(k_conv_wgrad, dim3(nblocks), dim3(256), 0, st, x, dy, H, W, plane0, nplanes,
-                     partial);
+                     int nplanes, int nblocks, float *partial, float *outv, int in_blocks,
+                     int out_blocks, hipStream_t st) {
+  if (in_blocks == 2 && out_blocks == 2)
+    hipLaunchKernelGGL((k_conv_wgrad<2, 2>), dim3(nblocks), dim3(256), 0, st, x, dy, H, W, plane0,
+                       nplanes, partial);
+  else if (in_blocks == 1 && out_blocks == 2)
+    hipLaunchKernelGGL((k_conv_wgrad<1, 2>), dim3(nblocks), dim3(256), 0, st, x, dy, H, W, plane0,
+                       nplanes, partial);
+  else if (in_blocks == 2 && out_blocks == 1)
+    hipLaunchKernelGGL((k_conv_wgrad<2, 1>), dim3(nblocks), dim3(256), 0, st, x, dy, H, W, plane0,
+                       nplanes, partial);
+  else
+    return hipErrorInvalidValue;
   const int len = 9 * CH * CH + CH;
   hipLaunchKernelGGL(k_reduce_partials, dim3((len + 255) / 256), dim3(256), 0, st, partial,
                      nblocks, len, outv);

@@ -53,8 +53,10 @@ hipError_t cnn_fused(const float *coef, const CnnPlanes &pl, int P, int H, int W
 hipError_t cnn_dz(const float *dcoef, const float *coef, const float *gain, const CnnPlanes &pl,
                   int P, int H, int W, uint16_t *dz, float *dzf, hipStream_t st);
 // weight gradient over planes [plane0, plane0 + nplanes) (local indices)
+// in_blocks / out_blocks: 16-channel blocks of x / dy that can be nonzero (1 or 2)
 hipError_t cnn_wgrad(const uint16_t *x, const uint16_t *dy, int H, int W, int plane0,
-                     int nplanes, int nblocks, float *partial, float *outv, hipStream_t st);
+                     int nplanes, int nblocks, float *partial, float *outv, int in_blocks,
+                     int out_blocks, hipStream_t st);
 hipError_t cnn_pack(const float *params, int J, int layer, int mode, uint16_t *Wp, int NB,
                     hipStream_t st);
 hipError_t cnn_adam(float *p, const float *g, float *m, float *v, int n, float lr, float b1,

@@ -241,8 +241,8 @@ int sl_cnn_backward(const sl_system *s, const float *params_dev, const void *pac
   for (int j = 0; j < J; ++j) {
     const int a = pl.start[j], n = pl.start[j + 1] - pl.start[j];
     const int nb = std::min(kWgradBlocks, n * tiles_per_plane);
-    CK(sl::cnn_wgrad(H2, DZ, H, W, a, n, nb, part, dW + (size_t)(3 * j + 2) * kWgradLen, st));
-    CK(sl::cnn_wgrad(H1, DA2, H, W, a, n, nb, part, dW + (size_t)(3 * j + 1) * kWgradLen, st));
+    CK(sl::cnn_wgrad(H2, DZ, H, W, a, n, nb, part, dW + (size_t)(3 * j + 2) * kWgradLen, 2, 1, st));
+    CK(sl::cnn_wgrad(H1, DA2, H, W, a, n, nb, part, dW + (size_t)(3 * j + 1) * kWgradLen, 2, 2, st));
   }
   uint16_t *DA1 = DZ;
   CK(sl::cnn_conv(DA2, pk.w2t, 2, nullptr, 0, pl, P, H, W, sl::CONV_MASKED, DA1, H1, nullptr,
@@ -251,7 +251,7 @@ int sl_cnn_backward(const sl_system *s, const float *params_dev, const void *pac
     const int a = pl.start[j], n = pl.start[j + 1] - pl.start[j];
     float *g1 = dW + (size_t)(3 * j) * kWgradLen;
     const int nb = std::min(kWgradBlocks, n * tiles_per_plane);
-    CK(sl::cnn_wgrad(X0, DA1, H, W, a, n, nb, part, g1, st));
+    CK(sl::cnn_wgrad(X0, DA1, H, W, a, n, nb, part, g1, 1, 2, st));
     CK(sl::cnn_grad_assemble(g1, dW + (size_t)(3 * j + 1) * kWgradLen,
                              dW + (size_t)(3 * j + 2) * kWgradLen, j, grads_dev, st));
   }
