@@ -26,6 +26,7 @@ namespace sl {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 constexpr int TH = 8, TW = 32;                 // output tile
 constexpr int HH = TH + 2, HW2 = TW + 2;       // input halo tile
@@ -62,14 +63,19 @@ __global__ void k_cnn_x0(const float *__restrict__ coef, CnnPlanes pl, uint16_t 
 // ---------------------------------------------------------------------------
 // 3x3 convolution, implicit GEMM on MFMA
 // ---------------------------------------------------------------------------
-// Wp: packed B operands [J][9][NB][64 lanes][8] bf16; bias [J][..] float
+// Wp: packed weight operands [J][9][NB][64 lanes][8] bf16; bias [J][..] float.
+// The weights are the A operand and the activation tile the B operand, so a
+// lane receives 4 consecutive output channels (16 nb + 4 (lane / 16) + i) of
+// one pixel (lane % 16) and stores them with one 8-byte write.  The halo tile
+// keeps pixels at a 40-channel stride (80 bytes) in LDS.
+constexpr int kConvCP = 40;
 template <int NB, int MODE>
 __global__ void __launch_bounds__(256)
 k_conv3x3(const uint16_t *__restrict__ in, const uint16_t *__restrict__ Wp,
           const float *__restrict__ bias, int bias_stride, CnnPlanes pl, int H, int W,
           uint16_t *__restrict__ out, const uint16_t *__restrict__ mask,
           const float *__restrict__ coef, float *__restrict__ coef_out, float *__restrict__ gain) {
-  __shared__ __attribute__((aligned(16))) uint16_t tile[HH * HW2 * CH];
+  __shared__ __attribute__((aligned(16))) uint16_t tile[HH * HW2 * kConvCP];
   const int p = blockIdx.z;
   const int ty0 = blockIdx.y * TH, tx0 = blockIdx.x * TW;
   const size_t HWn = (size_t)H * W;
@@ -83,9 +89,9 @@ k_conv3x3(const uint16_t *__restrict__ in, const uint16_t *__restrict__ Wp,
     uint4 v = make_uint4(0u, 0u, 0u, 0u);
     if (yy >= 0 && yy < H && xx >= 0 && xx < W)
       v = ((const uint4 *)(src + ((size_t)yy * W + xx) * CH))[part];
-    ((uint4 *)tile)[q] = v;
+    *(uint4 *)(tile + pix * kConvCP + 8 * part) = v;
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4;
   bf16x8 wb[9][NB];
   const uint16_t *wj = Wp + (size_t)j * 9 * NB * 64 * 8;
 #pragma unroll
@@ -93,6 +99,19 @@ k_conv3x3(const uint16_t *__restrict__ in, const uint16_t *__restrict__ Wp,
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
       wb[t][nb] = *(const bf16x8 *)(wj + (((size_t)t * NB + nb) * 64 + lane) * 8);
+  // accumulator initial values: the bias of each lane's 4 channels (layer 3
+  // has one output channel, channel 0)
+  f32x4 binit[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int ch = 16 * nb + 4 * g + e;
+      float v = 0.f;
+      if constexpr (MODE == CONV_RELU) v = bias[(size_t)j * bias_stride + ch];
+      if constexpr (MODE == CONV_GAIN) v = ch == 0 ? bias[(size_t)j * bias_stride] : 0.f;
+      binit[nb][e] = v;
+    }
   __syncthreads();
   // 16 pixel blocks (row r, half h) per tile; wave w takes blocks w, w+4, w+8, w+12
 #pragma unroll
@@ -101,41 +120,43 @@ k_conv3x3(const uint16_t *__restrict__ in, const uint16_t *__restrict__ Wp,
     const int r = blk >> 1, c0 = (blk & 1) * 16;
     f32x4 acc[NB];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int nb = 0; nb < NB; ++nb) acc[nb] = binit[nb];
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
       const int dy = t / 3, dx = t % 3;
       const int pix = (r + dy) * HW2 + c0 + (lane & 15) + dx;
-      const bf16x8 a = *(const bf16x8 *)(tile + pix * CH + 8 * (lane >> 4));
+      const bf16x8 xb = *(const bf16x8 *)(tile + pix * kConvCP + 8 * g);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wb[t][nb], acc[nb], 0, 0, 0);
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[t][nb], xb, acc[nb], 0, 0, 0);
     }
-    // epilogue: lane holds pixels m = 4 (lane / 16) + e of the block, channel lane % 16
-    const int yy = ty0 + r;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int xx = tx0 + c0 + 4 * (lane >> 4) + e;
-      if (yy >= H || xx >= W) continue;
-      const size_t opix = (size_t)p * HWn + (size_t)yy * W + xx;
+    const int yy = ty0 + r, xx = tx0 + c0 + (lane & 15);
+    if (yy >= H || xx >= W) continue;
+    const size_t opix = (size_t)p * HWn + (size_t)yy * W + xx;
+    if constexpr (MODE == CONV_RELU) {
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        const int ch = 16 * nb + (lane & 15);
-        float v = acc[nb][e];
-        if constexpr (MODE == CONV_RELU) {
-          v += bias[(size_t)j * bias_stride + ch];
-          out[opix * CH + ch] = v > 0.f ? f2bf(v) : (uint16_t)0;
-        } else if constexpr (MODE == CONV_MASKED) {
-          out[opix * CH + ch] = mask[opix * CH + ch] != 0 ? f2bf(v) : (uint16_t)0;
-        } else {   // CONV_GAIN: channel 0 only
-          if (ch == 0) {
-            v += bias[(size_t)j * bias_stride];
-            const float g = 1.0f / (1.0f + __expf(-v));
-            const size_t co = ((size_t)b * pl.R + i) * HWn + (size_t)yy * W + xx;
-            if (gain) gain[co] = g;
-            if (coef_out) coef_out[co] = g * coef[co];
-          }
-        }
+        bf16x4 o;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) o[e] = (__bf16)fmaxf(acc[nb][e], 0.f);
+        *(bf16x4 *)(out + opix * CH + 16 * nb + 4 * g) = o;
+      }
+    } else if constexpr (MODE == CONV_MASKED) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const uint2 mk = *(const uint2 *)(mask + opix * CH + 16 * nb + 4 * g);
+        const uint16_t *mh = (const uint16_t *)&mk;
+        bf16x4 o;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) o[e] = (__bf16)(mh[e] != 0 ? acc[nb][e] : 0.f);
+        *(bf16x4 *)(out + opix * CH + 16 * nb + 4 * g) = o;
+      }
+    } else {   // CONV_GAIN: channel 0 sits in lane group 0, element 0
+      if (g == 0) {
+        const float gv = 1.0f / (1.0f + __expf(-acc[0][0]));
+        const size_t co = ((size_t)b * pl.R + i) * HWn + (size_t)yy * W + xx;
+        if (gain) gain[co] = gv;
+        if (coef_out) coef_out[co] = gv * coef[co];
       }
     }
   }
@@ -182,8 +203,6 @@ constexpr int kLdsH1 = NH1 * CHP * 2, kLdsD3 = 16 * NH2 * 4, kLdsX0 = ((NX0 * 4 
 constexpr int kLdsFused = kLdsH1 + kLdsD3 + kLdsX0 + 2 * kLdsC;
 // blocks of the persistent grid per compute unit (160 KiB of LDS each)
 constexpr int kFusedBlocksPerCU = (2 * kLdsFused <= 160 * 1024) ? 2 : 1;
-
-typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 // relu(d) on 4 channels (the bias is the accumulator's initial value), zero
 // outside the image, rounded to bfloat16 (round to nearest even, as f2bf) by
