@@ -174,3 +174,68 @@ def uneven_sizes(n=64, seed=4000, choices=(256, 384, 512, 1024)):
     """Image sizes drawn uniformly from the given square sizes."""
     idx = np.random.default_rng(seed).integers(0, len(choices), n)
     return [int(choices[i]) for i in idx]
+
+
+# Occlusion masks (1 = known sample, 0 = missing) -----------------------------
+# The paper's inpainting masks (random 80 %, squares 28 %, text 25 %; random
+# 80 % and cubes 5 % for video) are drawn here from seeded generators:
+#   random:  default_rng([seed, 3]).random(shape) >= occlusion
+#   squares: axis-aligned squares, side ~ U{m/32 .. m/8}, top-left corner ~ U
+#            over the grid (clipped at the border), added until at least the
+#            target fraction is covered (cubes in 3D likewise)
+#   strokes: text-like strokes, each a 2-4 segment polyline of width
+#            ~ U{max(2, m/256) .. max(3, m/128)} pixels and segment length
+#            ~ U[m/64, m/16], drawn until the target fraction is covered
+
+def random_mask(shape, seed, occlusion=0.8):
+    return (np.random.default_rng([seed, 3]).random(shape) >= occlusion).astype(np.uint8)
+
+
+def squares_mask(shape, seed, occlusion=0.28):
+    rng = np.random.default_rng([seed, 4])
+    shape = tuple(int(s) for s in shape)
+    m = min(shape)
+    miss = np.zeros(shape, dtype=bool)
+    total = miss.size
+    while miss.sum() < occlusion * total:
+        side = int(rng.integers(max(1, m // 32), max(2, m // 8) + 1))
+        corner = [int(rng.integers(0, s)) for s in shape]
+        miss[tuple(slice(c, min(c + side, s)) for c, s in zip(corner, shape))] = True
+    return (~miss).astype(np.uint8)
+
+
+def strokes_mask(H, W, seed, occlusion=0.25):
+    rng = np.random.default_rng([seed, 5])
+    m = min(H, W)
+    miss = np.zeros((H, W), dtype=bool)
+    while miss.sum() < occlusion * H * W:
+        width = float(rng.integers(max(2, m // 256), max(3, m // 128) + 1))
+        p = rng.uniform([0, 0], [H, W])
+        for _ in range(int(rng.integers(2, 5))):
+            ang = rng.uniform(0.0, 2 * np.pi)
+            q = p + rng.uniform(m / 64, m / 16) * np.array([np.sin(ang), np.cos(ang)])
+            r = width / 2 + 1
+            y0, y1 = int(max(0, min(p[0], q[0]) - r)), int(min(H, max(p[0], q[0]) + r + 1))
+            x0, x1 = int(max(0, min(p[1], q[1]) - r)), int(min(W, max(p[1], q[1]) + r + 1))
+            if y1 > y0 and x1 > x0:
+                yy, xx = np.meshgrid(np.arange(y0, y1) + 0.5, np.arange(x0, x1) + 0.5, indexing="ij")
+                d = q - p
+                tt = np.clip(((yy - p[0]) * d[0] + (xx - p[1]) * d[1]) / max(d @ d, 1e-12), 0, 1)
+                dist2 = (yy - p[0] - tt * d[0]) ** 2 + (xx - p[1] - tt * d[1]) ** 2
+                miss[y0:y1, x0:x1] |= dist2 <= (width / 2) ** 2
+            p = q
+    return (~miss).astype(np.uint8)
+
+
+def inpainting_case(H, W, seed, kind):
+    """(clean cartoon image, mask) for one of the paper's mask types."""
+    clean = cartoon2d(H, W, seed)
+    if kind == "random":
+        mask = random_mask((H, W), seed)
+    elif kind == "squares":
+        mask = squares_mask((H, W), seed)
+    elif kind == "text":
+        mask = strokes_mask(H, W, seed)
+    else:
+        raise ValueError(kind)
+    return clean, mask
