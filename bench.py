@@ -109,6 +109,13 @@ def cpu_baseline(seconds, sigmas, K, H, W, J, levels):
                        f"(numpy.fft, single thread), filter build excluded, {el:.1f} s")
 
 
+def psnr(ref, est):
+    """PSNR in dB for images with unit peak: 20 log10(sqrt(N) / ||ref - est||_F)."""
+    import numpy as np
+    err = np.linalg.norm((np.asarray(ref, dtype=np.float64) - est).ravel())
+    return float(20.0 * np.log10(np.sqrt(np.size(ref)) / err))
+
+
 def time_call(fn, reps):
     """Mean milliseconds of fn() over reps calls (device events, one warm-up)."""
     import torch
@@ -208,6 +215,71 @@ def other_configs(reps=10):
     return out
 
 
+def inpainting_runs():
+    """Inpainting by iterative hard thresholding (Algorithm 3) at the paper's
+    settings, each run replayed from its HIP graph: one 512^2 image, R = 49,
+    300 iterations, per mask type (random 80 %, squares 28 %, text-like
+    strokes 25 %); a batch of 32 such images; one 192^3 video volume,
+    R = 292, 50 iterations, random 80 % mask.  Schedule delta_init = 4,
+    delta_min = 0.005 (normalised thresholds, images in [0, 1])."""
+    import numpy as np
+    import torch
+    from paper_1402_5670_amd import binding as Bd
+    from paper_1402_5670_amd import synthetic as syn
+    dev = torch.device("cuda:0")
+
+    out = {}
+    H, W, J, levels = (WORKLOAD[k] for k in ("H", "W", "J", "levels"))
+    its, dinit, dmin = 300, 4.0, 0.005
+    s2 = Bd.System((H, W), J, levels)
+    kinds = ("random", "squares", "text")
+    per = {}
+    for k, kind in enumerate(kinds):
+        clean, m = syn.inpainting_case(H, W, 900100 + k, kind)
+        fm = torch.from_numpy((clean * m)[None].astype(np.float32)).to(dev)
+        mg = torch.from_numpy(m[None]).to(dev)
+        dg = torch.full((1,), dinit, device=dev)
+        f = torch.empty_like(fm)
+        ms = time_call(lambda: s2.inpaint(fm, mg, dg, dmin, its, f=f, use_graph=True), 3)
+        res = f[0].cpu().numpy()
+        per[kind] = {"ms_per_300_iterations": round(ms, 3),
+                     "psnr_occluded_db": round(psnr(clean, clean * m), 2),
+                     "psnr_inpainted_db": round(psnr(clean, res), 2)}
+    ms1 = float(np.mean([v["ms_per_300_iterations"] for v in per.values()]))
+    out["image_512_R49_300it"] = {
+        "per_mask": per, "ms_per_iteration": round(ms1 / its, 4),
+        "coefficients_per_s": s2.R * H * W * its / ms1 * 1e3,
+        "paper_gpu_s_context": 78.7}
+    Bn = WORKLOAD["B"]
+    cases = [syn.inpainting_case(H, W, 900200 + b, kinds[b % 3]) for b in range(Bn)]
+    fm = torch.from_numpy(np.stack([c * m for c, m in cases]).astype(np.float32)).to(dev)
+    mg = torch.from_numpy(np.stack([m for _, m in cases])).to(dev)
+    dg = torch.full((Bn,), dinit, device=dev)
+    f = torch.empty_like(fm)
+    ms = time_call(lambda: s2.inpaint(fm, mg, dg, dmin, its, f=f, use_graph=True), 1)
+    out["batch_32x512_R49_300it"] = {"ms": round(ms, 2), "ms_per_iteration": round(ms / its, 4),
+                                     "images_per_s": round(Bn / ms * 1e3, 2),
+                                     "coefficients_per_s": Bn * s2.R * H * W * its / ms * 1e3}
+    del fm, mg, f, s2
+    torch.cuda.empty_cache()
+    dims, its3 = (192, 192, 192), 50
+    clean = syn.moving_ellipses_video(*dims, 5000)
+    m = syn.random_mask(dims, 5000)
+    s3 = Bd.System(dims, 3, [1, 1, 2])
+    fm = torch.from_numpy((clean * m)[None].astype(np.float32)).to(dev)
+    mg = torch.from_numpy(m[None]).to(dev)
+    dg = torch.full((1,), dinit, device=dev)
+    f = torch.empty_like(fm)
+    ms = time_call(lambda: s3.inpaint(fm, mg, dg, dmin, its3, f=f, use_graph=True), 1)
+    out["video_192_R292_50it"] = {
+        "ms": round(ms, 1), "ms_per_iteration": round(ms / its3, 3), "R": s3.R,
+        "coefficients_per_s": s3.R * 192 ** 3 * its3 / ms * 1e3,
+        "psnr_occluded_db": round(psnr(clean, clean * m), 2),
+        "psnr_inpainted_db": round(psnr(clean, f[0].cpu().numpy()), 2),
+        "paper_gpu_s_context": 3101}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,6 +289,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-other", action="store_true", help="skip the other configurations")
+    ap.add_argument("--no-inpaint", action="store_true", help="skip the inpainting runs")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -227,7 +300,6 @@ def main():
 
     import numpy as np
     import torch
-    from oracle import transform as T   # PSNR only
     from paper_1402_5670_amd import binding as Bd
     from paper_1402_5670_amd import synthetic as syn
 
@@ -302,9 +374,9 @@ def main():
                  "launches_per_step": launches, "traffic": measured_traffic(dom)})
 
     step_bytes = sum(pass_work(n, 0, H, W, R, Bn)[0] for n in rep)
-    psnr_noisy = float(np.mean([T.psnr(pairs[b][0], pairs[b][1]) for b in range(Bn)]))
+    psnr_noisy = float(np.mean([psnr(pairs[b][0], pairs[b][1]) for b in range(Bn)]))
     outn = out.cpu().numpy()
-    psnr_hard = float(np.mean([T.psnr(pairs[b][0], outn[b]) for b in range(Bn)]))
+    psnr_hard = float(np.mean([psnr(pairs[b][0], outn[b]) for b in range(Bn)]))
 
     res = {
         "metric": "coefficients/sec fwd+inv",
@@ -353,6 +425,8 @@ def main():
     if not args.no_other:
         del coeffs, scales, ws
         res["other_configs"] = other_configs()
+    if not args.no_inpaint:
+        res["inpainting"] = inpainting_runs()
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args.cpu_seconds, sig, K, H, W, J, levels)
     print(json.dumps(res))

@@ -149,6 +149,40 @@ int sl_denoise_fused(const sl_system *s, const float *x_dev, int batch, const fl
                      const float *K_host, float *out_dev, void *workspace_dev,
                      size_t workspace_bytes, void *stream);
 
+/* Inpainting by iterative hard thresholding (Algorithm 3; Section 5, image
+ * and video inpainting).  From f = 0 and with the mask M (1 = known sample),
+ * iteration t = 0..iterations-1 computes
+ *   g = M .* (f_masked - f) + f            (f_masked where M = 1, f elsewhere)
+ *   f = T^-1 T_delta_t T g                  (as sl_denoise_fused: subband i
+ *                                            kept iff |c_i| >= delta_t ||psi_i||_2,
+ *                                            the lowpass kept)
+ *   delta_t = delta_init[b] * lambda^t,    lambda = delta_min^(1/(iterations-1)),
+ * so the last iteration thresholds at delta_init * delta_min.  The threshold
+ * scale of iteration t is float32(delta_init[b] * float32(lambda^t)), lambda^t
+ * computed in double; everything else is float32.
+ *   f_masked_dev [B][dims] float32 (16-byte aligned); mask_dev [B][dims]
+ *     bytes, nonzero = known (4-byte aligned); delta_init_dev [B] float32;
+ *   t_begin, t_end: run iterations t_begin..t_end-1 of the schedule only
+ *     (0 <= t_begin <= t_end <= iterations).  f_dev [B][dims] float32
+ *     (16-byte aligned) holds on entry the estimate after t_begin iterations
+ *     (not read when t_begin = 0) and on exit the estimate after t_end, so a
+ *     long run can be split into segments with identical results;
+ *   use_graph: nonzero captures the launches of the call into a HIP graph,
+ *     instantiated on the first call and replayed by later calls with the
+ *     same arguments (pointers included); a system keeps the 4 most recent
+ *     graphs until sl_free_system.  Calls that share a system must not run
+ *     concurrently from several threads while building graphs.
+ *   workspace_dev of at least sl_inpaint_workspace_size(s, B) bytes
+ *     (16-byte aligned).
+ * Errors: SL_EINVAL for NULL or misaligned buffers, a bad iteration range
+ * or delta_min < 0; SL_ENOMEM for a short workspace; SL_EHIP for a launch
+ * or graph failure (the estimate is then undefined).                       */
+int sl_inpaint_workspace_size(const sl_system *s, int batch, size_t *bytes_out);
+int sl_inpaint(const sl_system *s, const float *f_masked_dev, const unsigned char *mask_dev,
+               int batch, const float *delta_init_dev, double delta_min, int iterations,
+               int t_begin, int t_end, float *f_dev, int use_graph, void *workspace_dev,
+               size_t workspace_bytes, void *stream);
+
 /* Adjoint of sl_inverse: c_i = IDFT(psi_hat_i / Psi_hat .* DFT(r)) for every
  * subband, i.e. the forward transform with the dual filters of eq.
  * dual_filter.  Used to back-propagate an image-domain loss through the

@@ -73,6 +73,12 @@ _SIGS = {
     "sl_denoise_fused": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                           ctypes.c_void_p], ctypes.c_int),
+    "sl_inpaint_workspace_size": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
+                                  ctypes.c_int),
+    "sl_inpaint": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                    ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                    ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
+                    ctypes.c_void_p], ctypes.c_int),
     "sl_inverse_adjoint": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                             ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
     "sl_cnn_packed_bytes": ([ctypes.c_int], ctypes.c_size_t),
@@ -342,6 +348,39 @@ class System:
                                      ctypes.cast(Kh, ctypes.c_void_p), _ptr(out), _ptr(ws),
                                      ws.numel(), _stream()))
         return out
+
+    def inpaint_workspace_bytes(self, batch):
+        n = ctypes.c_size_t()
+        check(lib().sl_inpaint_workspace_size(self._h, int(batch), ctypes.byref(n)))
+        return n.value
+
+    def inpaint(self, f_masked, mask, delta_init, delta_min, iterations, t_begin=0, t_end=None,
+                f=None, use_graph=False, workspace=None):
+        """Iterations t_begin..t_end-1 of inpainting by iterative hard
+        thresholding (sl_inpaint).  mask: uint8 [B, dims], nonzero = known;
+        delta_init: float32 [B] on the device; f: the estimate after t_begin
+        iterations (updated in place and returned)."""
+        import torch
+        self._check_x(f_masked)
+        B = f_masked.shape[0]
+        if not (mask.dtype == torch.uint8 and mask.is_cuda and mask.is_contiguous()
+                and mask.shape == f_masked.shape):
+            raise ValueError("mask must be a contiguous uint8 CUDA tensor shaped like f_masked")
+        if f is None:
+            f = torch.empty_like(f_masked)
+        self._check_x(f)
+        if workspace is None:
+            n = self.inpaint_workspace_bytes(B)
+            workspace = self._ws.get(("inpaint", str(f.device)))
+            if workspace is None or workspace.numel() < n:
+                workspace = torch.empty(n, dtype=torch.uint8, device=f.device)
+                self._ws[("inpaint", str(f.device))] = workspace
+        t_end = iterations if t_end is None else t_end
+        check(lib().sl_inpaint(self._h, _ptr(f_masked), _ptr(mask), B, _ptr(delta_init),
+                               float(delta_min), int(iterations), int(t_begin), int(t_end),
+                               _ptr(f), 1 if use_graph else 0, _ptr(workspace),
+                               workspace.numel(), _stream()))
+        return f
 
 
 CNN_PARAMS = 10145

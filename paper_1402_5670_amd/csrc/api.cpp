@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -13,6 +14,7 @@
 #include "../../include/shearlet.h"
 #include "dispatch.hpp"
 #include "host_filters.hpp"
+#include "inpaint.hpp"
 #include "system.hpp"
 
 namespace {
@@ -205,9 +207,12 @@ struct Timing {
   }
 } g_timing;
 
+// set while sl_inpaint captures a graph: no timing events go into it
+thread_local bool g_capturing = false;
+
 template <class F>
 hipError_t timed(int pass, hipStream_t st, F &&launch) {
-  if (!g_timing.on) return launch();
+  if (!g_timing.on || g_capturing) return launch();
   hipEvent_t a = g_timing.get(), b = g_timing.get();
   (void)hipEventRecord(a, st);
   hipError_t e = launch();
@@ -264,6 +269,111 @@ int inverse3d(const sl_system *s, const void *coef, const float *scales, int bat
     }
   SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, ACC, ACC, batch * D, true, st));
   SL_LAUNCH(P_ROWS_REAL_IFFT, st, sl::launch_rows_real_ifft(vr, ACC, x, batch, st));
+  return SL_OK;
+}
+
+
+// Forward transform, hard threshold and inverse transform without
+// materialising the coefficients (the body of sl_denoise_fused and of every
+// inpainting iteration).  Arguments are validated by the callers.
+int denoise_fused_run(const sl_system *s, const float *x_dev, int batch, const sl::ThrArgs &thr,
+                      float *out_dev, char *ws, hipStream_t st) {
+  const Layout L = layout(s, batch);
+  float2 *F = (float2 *)(ws + L.off_F);
+  float2 *ACC = (float2 *)(ws + L.off_acc);
+  float2 *T = (float2 *)(ws + L.off_chunk);
+  const float inv_n = 1.0f / (float)s->cfg.npix();
+  int nb, np;
+  chunk_plan(s, batch, nb, np);
+  const int P = (s->R + 1) / 2;
+  if (s->cfg.ndim == 3) {
+    const int D = (int)s->cfg.dims[0], H = (int)s->cfg.dims[1], W = (int)s->cfg.dims[2];
+    const sl::Sys2D vr = view2d(s, D * H, W, 0, W);
+    const sl::Sys2D vy = view2d(s, H, W, H, 0);
+    const sl::Sys2D vz = view2d(s, D, H * W, D, 0);
+    const sl::Sys3D v3 = view3d(s);
+    SL_LAUNCH(P_ROWS_REAL_FFT, st, sl::launch_rows_real_fft(vr, x_dev, F, nullptr, batch, st));
+    SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, F, F, batch * D, false, st));
+    SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vz, F, F, batch, false, st));
+    for (int b0 = 0; b0 < batch; b0 += nb)
+      for (int p0 = 0; p0 < P; p0 += np) {
+        sl::Chunk c{b0, std::min(nb, batch - b0), p0, std::min(np, P - p0)};
+        SL_LAUNCH(P_COLS_FILTER_IFFT, st, sl::launch_z_filter_ifft(v3, F, T, c, st));
+        SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, T, T, c.nb * c.np * D, true, st));
+        SL_LAUNCH(P_ROWS_THR, st, sl::launch_rows_thr(vr, T, inv_n, c, thr, st));
+        SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, T, T, c.nb * c.np * D, false, st));
+        SL_LAUNCH(P_COLS_FFT_ACC, st,
+                  sl::launch_z_fft_acc(v3, T, ACC, c, p0 == 0, p0 + c.np == P, st));
+      }
+    SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, ACC, ACC, batch * D, true, st));
+    SL_LAUNCH(P_ROWS_REAL_IFFT, st, sl::launch_rows_real_ifft(vr, ACC, out_dev, batch, st));
+    return SL_OK;
+  }
+  const sl::Sys2D v = view2d(s);
+  SL_LAUNCH(P_ROWS_REAL_FFT, st, sl::launch_rows_real_fft(v, x_dev, F, nullptr, batch, st));
+  SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(v, F, F, batch, false, st));
+  for (int b0 = 0; b0 < batch; b0 += nb)
+    for (int p0 = 0; p0 < P; p0 += np) {
+      sl::Chunk c{b0, std::min(nb, batch - b0), p0, std::min(np, P - p0)};
+      SL_LAUNCH(P_COLS_FILTER_IFFT, st, sl::launch_cols_filter_ifft(v, F, T, c, st));
+      SL_LAUNCH(P_ROWS_THR, st, sl::launch_rows_thr(v, T, inv_n, c, thr, st));
+      SL_LAUNCH(P_COLS_FFT_ACC, st, sl::launch_cols_fft_acc(v, T, ACC, c, p0 == 0, p0 + c.np == P, st));
+    }
+  SL_LAUNCH(P_ROWS_REAL_IFFT, st, sl::launch_rows_real_ifft(v, ACC, out_dev, batch, st));
+  return SL_OK;
+}
+
+// Inpainting workspace: the transform's, then g [B][npix] float32 (the
+// iteration's input) and sigma [B] float32 (the iteration's threshold scale).
+struct InpaintLayout {
+  size_t base, off_g, off_sigma, total;
+};
+
+InpaintLayout inpaint_layout(const sl_system *s, int B) {
+  InpaintLayout L;
+  L.base = layout(s, B).total;
+  L.off_g = L.base;
+  L.off_sigma = align_up(L.off_g + 4ull * (size_t)s->cfg.npix() * B);
+  L.total = align_up(L.off_sigma + 4ull * B);
+  return L;
+}
+
+struct InpaintArgs {
+  const float *fm;
+  const uint8_t *mask;
+  int batch;
+  const float *delta_init;
+  double delta_min;
+  int iterations, t_begin, t_end;
+  float *f;
+  char *ws;
+};
+
+// threshold factor of iteration t: lambda^t, lambda = delta_min^(1/(iterations-1))
+float schedule_factor(double delta_min, int iterations, int t) {
+  if (iterations <= 1 || t == 0) return 1.0f;
+  const double lam = std::pow(delta_min, 1.0 / (double)(iterations - 1));
+  return (float)std::pow(lam, (double)t);
+}
+
+int inpaint_launches(const sl_system *s, const InpaintArgs &a, hipStream_t st) {
+  const InpaintLayout L = inpaint_layout(s, a.batch);
+  float *g = (float *)(a.ws + L.off_g);
+  float *sigma = (float *)(a.ws + L.off_sigma);
+  sl::ThrArgs thr{};
+  thr.sigma = sigma;
+  thr.l2 = s->d_l2;
+  thr.jof = s->d_jof;
+  for (int j = 0; j < s->cfg.J; ++j) thr.K[j] = 1.0f;
+  const size_t n = (size_t)s->cfg.npix() * a.batch;
+  for (int t = a.t_begin; t < a.t_end; ++t) {
+    SL_LAUNCH(P_AUX, st,
+              sl::launch_inpaint_mix(a.fm, a.mask, a.f, g, n, t == 0, a.delta_init,
+                                     schedule_factor(a.delta_min, a.iterations, t), sigma,
+                                     a.batch, st));
+    int rc = denoise_fused_run(s, g, a.batch, thr, a.f, a.ws, st);
+    if (rc) return rc;
+  }
   return SL_OK;
 }
 
@@ -423,6 +533,10 @@ int sl_build_system(const sl_config *cfg, sl_system **out) {
 
 void sl_free_system(sl_system *s) {
   if (!s) return;
+  for (auto &g : s->graphs) {
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipGraphDestroy(g.graph);
+  }
   for (void *p : s->allocs) (void)hipFree(p);
   delete s;
 }
@@ -542,51 +656,8 @@ int sl_denoise_fused(const sl_system *s, const float *x_dev, int batch, const fl
   thr.l2 = s->d_l2;
   thr.jof = s->d_jof;
   for (int j = 0; j < s->cfg.J; ++j) thr.K[j] = K_host[j];
-  hipStream_t st = (hipStream_t)stream;
-  const Layout L = layout(s, batch);
-  char *ws = (char *)workspace_dev;
-  float2 *F = (float2 *)(ws + L.off_F);
-  float2 *ACC = (float2 *)(ws + L.off_acc);
-  float2 *T = (float2 *)(ws + L.off_chunk);
-  const float inv_n = 1.0f / (float)s->cfg.npix();
-  int nb, np;
-  chunk_plan(s, batch, nb, np);
-  const int P = (s->R + 1) / 2;
-  if (s->cfg.ndim == 3) {
-    const int D = (int)s->cfg.dims[0], H = (int)s->cfg.dims[1], W = (int)s->cfg.dims[2];
-    const sl::Sys2D vr = view2d(s, D * H, W, 0, W);
-    const sl::Sys2D vy = view2d(s, H, W, H, 0);
-    const sl::Sys2D vz = view2d(s, D, H * W, D, 0);
-    const sl::Sys3D v3 = view3d(s);
-    SL_LAUNCH(P_ROWS_REAL_FFT, st, sl::launch_rows_real_fft(vr, x_dev, F, nullptr, batch, st));
-    SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, F, F, batch * D, false, st));
-    SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vz, F, F, batch, false, st));
-    for (int b0 = 0; b0 < batch; b0 += nb)
-      for (int p0 = 0; p0 < P; p0 += np) {
-        sl::Chunk c{b0, std::min(nb, batch - b0), p0, std::min(np, P - p0)};
-        SL_LAUNCH(P_COLS_FILTER_IFFT, st, sl::launch_z_filter_ifft(v3, F, T, c, st));
-        SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, T, T, c.nb * c.np * D, true, st));
-        SL_LAUNCH(P_ROWS_THR, st, sl::launch_rows_thr(vr, T, inv_n, c, thr, st));
-        SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, T, T, c.nb * c.np * D, false, st));
-        SL_LAUNCH(P_COLS_FFT_ACC, st,
-                  sl::launch_z_fft_acc(v3, T, ACC, c, p0 == 0, p0 + c.np == P, st));
-      }
-    SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, ACC, ACC, batch * D, true, st));
-    SL_LAUNCH(P_ROWS_REAL_IFFT, st, sl::launch_rows_real_ifft(vr, ACC, out_dev, batch, st));
-    return SL_OK;
-  }
-  const sl::Sys2D v = view2d(s);
-  SL_LAUNCH(P_ROWS_REAL_FFT, st, sl::launch_rows_real_fft(v, x_dev, F, nullptr, batch, st));
-  SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(v, F, F, batch, false, st));
-  for (int b0 = 0; b0 < batch; b0 += nb)
-    for (int p0 = 0; p0 < P; p0 += np) {
-      sl::Chunk c{b0, std::min(nb, batch - b0), p0, std::min(np, P - p0)};
-      SL_LAUNCH(P_COLS_FILTER_IFFT, st, sl::launch_cols_filter_ifft(v, F, T, c, st));
-      SL_LAUNCH(P_ROWS_THR, st, sl::launch_rows_thr(v, T, inv_n, c, thr, st));
-      SL_LAUNCH(P_COLS_FFT_ACC, st, sl::launch_cols_fft_acc(v, T, ACC, c, p0 == 0, p0 + c.np == P, st));
-    }
-  SL_LAUNCH(P_ROWS_REAL_IFFT, st, sl::launch_rows_real_ifft(v, ACC, out_dev, batch, st));
-  return SL_OK;
+  return denoise_fused_run(s, x_dev, batch, thr, out_dev, (char *)workspace_dev,
+                           (hipStream_t)stream);
 }
 
 int sl_denoise(const sl_system *s, const float *x_dev, int batch, const float *sigma_dev,
@@ -598,6 +669,92 @@ int sl_denoise(const sl_system *s, const float *x_dev, int batch, const float *s
   if (rc) return rc;
   return sl_inverse(s, coeffs_dev, scales_dev, batch, sigma_dev, K_host, out_dev, workspace_dev,
                     workspace_bytes, stream);
+}
+
+
+int sl_inpaint_workspace_size(const sl_system *s, int batch, size_t *bytes_out) {
+  if (!s || !bytes_out) return fail(SL_EINVAL, "NULL argument");
+  if (batch < 1) return fail(SL_EINVAL, "batch must be >= 1");
+  *bytes_out = inpaint_layout(s, batch).total;
+  return SL_OK;
+}
+
+int sl_inpaint(const sl_system *s, const float *f_masked_dev, const unsigned char *mask_dev,
+               int batch, const float *delta_init_dev, double delta_min, int iterations,
+               int t_begin, int t_end, float *f_dev, int use_graph, void *workspace_dev,
+               size_t workspace_bytes, void *stream) {
+  if (!s) return fail(SL_EINVAL, "system is NULL");
+  if (batch < 1 || batch > 65535) return fail(SL_EINVAL, "batch must be in 1..65535");
+  if (!f_masked_dev || !mask_dev || !delta_init_dev || !f_dev || !workspace_dev)
+    return fail(SL_EINVAL, "NULL buffer");
+  if (iterations < 1) return fail(SL_EINVAL, "iterations must be >= 1");
+  if (t_begin < 0 || t_end < t_begin || t_end > iterations)
+    return fail(SL_EINVAL, "need 0 <= t_begin <= t_end <= iterations");
+  if (!(delta_min >= 0.0) || !std::isfinite(delta_min))
+    return fail(SL_EINVAL, "delta_min must be finite and >= 0");
+  if (((uintptr_t)f_masked_dev | (uintptr_t)f_dev | (uintptr_t)workspace_dev) & 15u)
+    return fail(SL_EINVAL, "f_masked, f and the workspace must be 16-byte aligned");
+  if ((uintptr_t)mask_dev & 3u) return fail(SL_EINVAL, "mask must be 4-byte aligned");
+  if (s->cfg.J > sl::kMaxScales) return fail(SL_EUNSUPPORTED, "too many scales");
+  if (s->cfg.npix() % 4) return fail(SL_EUNSUPPORTED, "the sample count must be a multiple of 4");
+  const InpaintLayout L = inpaint_layout(s, batch);
+  if (workspace_bytes < L.total)
+    return fail(SL_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != s->device)
+    return fail(SL_EINVAL, "the current HIP device is not the system's device");
+  if (t_begin == t_end) return SL_OK;
+  InpaintArgs a{f_masked_dev, mask_dev, batch,   delta_init_dev, delta_min,
+                iterations,   t_begin,  t_end,   f_dev,          (char *)workspace_dev};
+  hipStream_t st = (hipStream_t)stream;
+  if (!use_graph) return inpaint_launches(s, a, st);
+
+  auto *ms = const_cast<sl_system *>(s);
+  uint64_t dm_bits;
+  std::memcpy(&dm_bits, &delta_min, sizeof(dm_bits));
+  std::vector<uint64_t> key = {(uint64_t)(uintptr_t)f_masked_dev, (uint64_t)(uintptr_t)mask_dev,
+                               (uint64_t)batch, (uint64_t)(uintptr_t)delta_init_dev, dm_bits,
+                               (uint64_t)iterations, (uint64_t)t_begin, (uint64_t)t_end,
+                               (uint64_t)(uintptr_t)f_dev, (uint64_t)(uintptr_t)workspace_dev,
+                               (uint64_t)s->chunk_cap};
+  std::lock_guard<std::mutex> lock(ms->graph_mu);
+  for (auto &gr : ms->graphs)
+    if (gr.key == key) {
+      SL_TRY(hipGraphLaunch(gr.exec, st));
+      return SL_OK;
+    }
+  // capture the iterations on a private stream, instantiate, keep
+  hipStream_t cs = nullptr;
+  SL_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return hip_fail(e, "hipStreamBeginCapture");
+  }
+  g_capturing = true;
+  int rc = inpaint_launches(s, a, cs);
+  g_capturing = false;
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(cs, &graph);
+  (void)hipStreamDestroy(cs);
+  if (rc || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc ? rc : hip_fail(e, "hipStreamEndCapture");
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  if (ms->graphs.size() >= 4) {
+    (void)hipGraphExecDestroy(ms->graphs.front().exec);
+    (void)hipGraphDestroy(ms->graphs.front().graph);
+    ms->graphs.erase(ms->graphs.begin());
+  }
+  ms->graphs.push_back({key, graph, exec});
+  SL_TRY(hipGraphLaunch(exec, st));
+  return SL_OK;
 }
 
 int sl_timing_enable(int on) {

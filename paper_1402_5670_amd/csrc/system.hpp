@@ -3,7 +3,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "dispatch.hpp"
@@ -25,6 +27,15 @@ struct sl_system {
   float *d_tab3 = nullptr;        // 3D: factor tables
   std::map<int, float2 *> d_tw;
   std::vector<void *> allocs;
+  // instantiated inpainting graphs, keyed by every argument they bake in
+  // (newest last; a few are kept)
+  struct Graph {
+    std::vector<uint64_t> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<Graph> graphs;
+  std::mutex graph_mu;
 };
 
 #include <string>
