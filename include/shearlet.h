@@ -106,7 +106,8 @@ void sl_free_system(sl_system *s);
 int sl_system_num_subbands(const sl_system *s, int *R_out);
 int sl_system_subband(const sl_system *s, int i, sl_subband *out);
 
-/* Device bytes of workspace needed by forward/inverse/denoise for a batch.  */
+/* Device bytes of workspace needed by forward/inverse/denoise for a batch.
+ * Every workspace pointer must be 16-byte aligned (SL_EINVAL otherwise).   */
 int sl_workspace_size(const sl_system *s, int batch, size_t *bytes_out);
 
 /* ---- transforms --------------------------------------------------------- */

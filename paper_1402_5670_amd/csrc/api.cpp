@@ -93,9 +93,13 @@ void chunk_plan(const sl_system *s, int B, int &nb, int &np) {
 // Workspace: spectrum F (also the inverse's accumulator) [B] complex planes,
 // a second accumulator [B] used by sl_denoise_fused (F must survive every
 // chunk there), the chunk of pair planes, per-image max |x|.
+// Partial sums of the 2D inverse accumulation when its pair loop is split
+// into groups (small batches): [groups - 1][B] complex planes.
 struct Layout {
-  size_t off_F, off_acc, off_chunk, off_xmax, total;
+  size_t off_F, off_acc, off_chunk, off_xmax, off_part, total;
 };
+
+int inv_groups(const sl_system *s, int B);
 
 Layout layout(const sl_system *s, int B) {
   int nb, np;
@@ -106,7 +110,8 @@ Layout layout(const sl_system *s, int B) {
   L.off_acc = align_up(plane * B);
   L.off_chunk = align_up(L.off_acc + plane * B);
   L.off_xmax = align_up(L.off_chunk + plane * (size_t)nb * np);
-  L.total = align_up(L.off_xmax + 4ull * B);
+  L.off_part = align_up(L.off_xmax + 4ull * B);
+  L.total = align_up(L.off_part + plane * B * (size_t)(inv_groups(s, B) - 1));
   return L;
 }
 
@@ -122,6 +127,7 @@ sl::Sys2D view2d(const sl_system *s, int H, int W, int nH, int nW) {
   v.filt = s->d_filt;
   v.psi = s->d_psi;
   v.l1 = s->d_l1;
+  v.num_cu = s->num_cu;
   v.twH = nH ? s->d_tw.at(nH) : nullptr;
   v.twW = nW ? s->d_tw.at(nW) : nullptr;
   return v;
@@ -130,6 +136,13 @@ sl::Sys2D view2d(const sl_system *s, int H, int W, int nH, int nW) {
 sl::Sys2D view2d(const sl_system *s) {
   int H = (int)s->cfg.dims[0], W = (int)s->cfg.dims[1];
   return view2d(s, H, W, H, W);
+}
+
+int inv_groups(const sl_system *s, int B) {
+  if (s->cfg.ndim != 2) return 1;
+  int nb, np;
+  chunk_plan(s, B, nb, np);
+  return sl::inv_pair_groups(view2d(s), nb, np);
 }
 
 sl::Sys3D view3d(const sl_system *s) {
@@ -151,6 +164,7 @@ int check_call(const sl_system *s, int batch, const void *a, const void *b, void
   if (!s) return fail(SL_EINVAL, "system is NULL");
   if (batch < 1 || batch > 65535) return fail(SL_EINVAL, "batch must be in 1..65535");
   if (!a || !b || !ws) return fail(SL_EINVAL, "NULL buffer");
+  if ((uintptr_t)ws & 15u) return fail(SL_EINVAL, "the workspace must be 16-byte aligned");
   size_t need = layout(s, batch).total;
   if (ws_bytes < need)
     return fail(SL_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
@@ -310,6 +324,8 @@ int denoise_fused_run(const sl_system *s, const float *x_dev, int batch, const s
     return SL_OK;
   }
   const sl::Sys2D v = view2d(s);
+  const int G = inv_groups(s, batch);
+  float2 *part = (float2 *)(ws + L.off_part);
   SL_LAUNCH(P_ROWS_REAL_FFT, st, sl::launch_rows_real_fft(v, x_dev, F, nullptr, batch, st));
   SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(v, F, F, batch, false, st));
   for (int b0 = 0; b0 < batch; b0 += nb)
@@ -317,8 +333,10 @@ int denoise_fused_run(const sl_system *s, const float *x_dev, int batch, const s
       sl::Chunk c{b0, std::min(nb, batch - b0), p0, std::min(np, P - p0)};
       SL_LAUNCH(P_COLS_FILTER_IFFT, st, sl::launch_cols_filter_ifft(v, F, T, c, st));
       SL_LAUNCH(P_ROWS_THR, st, sl::launch_rows_thr(v, T, inv_n, c, thr, st));
-      SL_LAUNCH(P_COLS_FFT_ACC, st, sl::launch_cols_fft_acc(v, T, ACC, c, p0 == 0, p0 + c.np == P, st));
+      SL_LAUNCH(P_COLS_FFT_ACC, st,
+                sl::launch_cols_fft_acc(v, T, ACC, part, G, batch, c, p0 == 0, p0 + c.np == P, st));
     }
+  if (G > 1) SL_LAUNCH(P_COLS_FFT_ACC, st, sl::launch_cols_acc_finish(v, ACC, part, G, batch, st));
   SL_LAUNCH(P_ROWS_REAL_IFFT, st, sl::launch_rows_real_ifft(v, ACC, out_dev, batch, st));
   return SL_OK;
 }
@@ -634,12 +652,16 @@ int sl_inverse(const sl_system *s, const void *coeffs_dev, const float *scales_d
   int nb, np;
   chunk_plan(s, batch, nb, np);
   const int P = (s->R + 1) / 2;
+  const int G = inv_groups(s, batch);
+  float2 *part = (float2 *)(ws + L.off_part);
   for (int b0 = 0; b0 < batch; b0 += nb)
     for (int p0 = 0; p0 < P; p0 += np) {
       sl::Chunk c{b0, std::min(nb, batch - b0), p0, std::min(np, P - p0)};
       SL_LAUNCH(P_ROWS_COEF_FFT, st, sl::launch_rows_coef_fft(v, coeffs_dev, scales_dev, U, c, thr, st));
-      SL_LAUNCH(P_COLS_FFT_ACC, st, sl::launch_cols_fft_acc(v, U, ACC, c, p0 == 0, p0 + c.np == P, st));
+      SL_LAUNCH(P_COLS_FFT_ACC, st,
+                sl::launch_cols_fft_acc(v, U, ACC, part, G, batch, c, p0 == 0, p0 + c.np == P, st));
     }
+  if (G > 1) SL_LAUNCH(P_COLS_FFT_ACC, st, sl::launch_cols_acc_finish(v, ACC, part, G, batch, st));
   SL_LAUNCH(P_ROWS_REAL_IFFT, st, sl::launch_rows_real_ifft(v, ACC, x_dev, batch, st));
   return SL_OK;
 }

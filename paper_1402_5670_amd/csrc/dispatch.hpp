@@ -21,6 +21,7 @@ struct ThrArgs {
 // Per-call view of the 2D system tables.
 struct Sys2D {
   int H, W, R, dtype;
+  int num_cu;               // compute units of the device (grid sizing)
   const float *filt;        // [R][H][W]
   const float *psi;         // [H][W]  Psi_hat
   const float *l1;          // [R]
@@ -63,8 +64,14 @@ hipError_t launch_rows_thr(const Sys2D &s, float2 *T, float inv_n, Chunk c, cons
                            hipStream_t st);
 // U[chunk] -> ACC (column DFT, multiply by the filter pair, sum over pairs);
 // the last chunk divides by Psi_hat and applies the column inverse DFT.
-hipError_t launch_cols_fft_acc(const Sys2D &s, const float2 *U, float2 *ACC, Chunk c, bool first,
-                               bool last, hipStream_t st);
+// With G > 1 pair groups (inv_pair_groups) group z sums into part[z - 1]
+// ([G - 1][Btot] planes), and launch_cols_acc_finish completes the sum, the
+// division and the column inverse DFT after the last chunk.
+int inv_pair_groups(const Sys2D &s, int nb, int np);
+hipError_t launch_cols_fft_acc(const Sys2D &s, const float2 *U, float2 *ACC, float2 *part, int G,
+                               int Btot, Chunk c, bool first, bool last, hipStream_t st);
+hipError_t launch_cols_acc_finish(const Sys2D &s, float2 *ACC, const float2 *part, int G, int B,
+                                  hipStream_t st);
 // ACC -> x (row inverse DFT, real part, 1/(HW))
 hipError_t launch_rows_real_ifft(const Sys2D &s, const float2 *V, float *x, int B, hipStream_t st);
 

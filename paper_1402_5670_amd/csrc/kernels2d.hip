@@ -287,6 +287,11 @@ k_cols_filter_ifft3(const float2 *__restrict__ F, const float *__restrict__ filt
   const bool ok = col < W;
   const unsigned o0 = (unsigned)t * W + (ok ? col : 0), se = (unsigned)NT * W;
   const size_t plane = (size_t)N * W;
+  // pairs [q0, q1) of the chunk: gridDim.z groups split the pair loop when
+  // the column tiles alone would leave compute units idle (small batches)
+  const int per = (np + (int)gridDim.z - 1) / (int)gridDim.z;
+  const int q0 = (int)blockIdx.z * per, q1 = min(np, q0 + per);
+  if (q0 >= q1) return;
   float2 f[BT][E];
 #pragma unroll
   for (int bt = 0; bt < BT; ++bt) {
@@ -310,8 +315,8 @@ k_cols_filter_ifft3(const float2 *__restrict__ F, const float *__restrict__ filt
     }
   };
   float a[E], bb[E];
-  load_pair(0, a, bb);
-  for (int pp = 0; pp < np; ++pp) {
+  load_pair(q0, a, bb);
+  for (int pp = q0; pp < q1; ++pp) {
     float2 v[BT][E];
 #pragma unroll
     for (int bt = 0; bt < BT; ++bt)
@@ -319,7 +324,7 @@ k_cols_filter_ifft3(const float2 *__restrict__ F, const float *__restrict__ filt
       for (int e = 0; e < E; ++e)
         v[bt][e] = make_float2(f[bt][e].x * a[e] - f[bt][e].y * bb[e],
                                f[bt][e].y * a[e] + f[bt][e].x * bb[e]);
-    if (pp + 1 < np) load_pair(pp + 1, a, bb);   // lands during the FFTs below
+    if (pp + 1 < q1) load_pair(pp + 1, a, bb);   // lands during the FFTs below
 #pragma unroll
     for (int bt = 0; bt < BT; ++bt) {
       const int bl = blockIdx.y * BT + bt;
@@ -578,8 +583,9 @@ k_rows_thr(float2 *__restrict__ T, int H, int R, int b0, int p0, int np, float i
 template <int N, int BT>
 __global__ void __launch_bounds__(CTile<N>::THREADS)
 k_cols_fft_acc(const float2 *__restrict__ U, const float *__restrict__ filt,
-               const float *__restrict__ psi, float2 *__restrict__ ACC, int W, int R, int b0,
-               int nb, int p0, int np, int first, int last, const float2 *__restrict__ tw) {
+               const float *__restrict__ psi, float2 *__restrict__ ACC, float2 *__restrict__ part,
+               int Btot, int W, int R, int b0, int nb, int p0, int np, int first, int last,
+               const float2 *__restrict__ tw) {
   constexpr int NT = CTile<N>::NT, M = CTile<N>::M, E = CTile<N>::E;
   using PL = typename CTile<N>::PL;
   __shared__ float2 lds[M * N];
@@ -588,16 +594,23 @@ k_cols_fft_acc(const float2 *__restrict__ U, const float *__restrict__ filt,
   const bool ok = col < W;
   const int cc = ok ? col : 0;
   const size_t plane = (size_t)N * W;
+  // pair group z sums pairs [q0, q1) of the chunk into its own partial sum:
+  // ACC for z = 0, part[z - 1] ([Btot] planes each) otherwise; with several
+  // groups k_cols_acc_finish adds the partial sums after the last chunk.  A
+  // group with no pair in this chunk still initialises its partial sum.
+  const int per = (np + (int)gridDim.z - 1) / (int)gridDim.z;
+  const int q0 = (int)blockIdx.z * per, q1 = min(np, q0 + per);
+  float2 *dst = blockIdx.z == 0 ? ACC : part + (size_t)(blockIdx.z - 1) * Btot * plane;
   float2 acc[BT][E];
 #pragma unroll
   for (int bt = 0; bt < BT; ++bt) {
     const int bl = blockIdx.y * BT + bt;
-    const float2 *accp = ACC + (size_t)(b0 + (bl < nb ? bl : 0)) * plane + cc;
+    const float2 *accp = dst + (size_t)(b0 + (bl < nb ? bl : 0)) * plane + cc;
 #pragma unroll
     for (int e = 0; e < E; ++e)
       acc[bt][e] = first ? make_float2(0.f, 0.f) : accp[(size_t)(t + e * NT) * W];
   }
-  for (int pp = 0; pp < np; ++pp) {
+  for (int pp = q0; pp < q1; ++pp) {
     const int ia = 2 * (p0 + pp), ib = ia + 1;
     const float *fa = filt + (size_t)ia * plane + cc;
     const float *fb = filt + (size_t)(ib < R ? ib : ia) * plane + cc;
@@ -637,10 +650,56 @@ k_cols_fft_acc(const float2 *__restrict__ U, const float *__restrict__ filt,
       fft_line_p<PL, true>(acc[bt], t, LdsLine{lds + m, M}, tw);
     }
     if (ok && bl < nb) {
-      float2 *accp = ACC + (size_t)(b0 + bl) * plane + cc;
+      float2 *accp = dst + (size_t)(b0 + bl) * plane + cc;
 #pragma unroll
       for (int e = 0; e < E; ++e) accp[(size_t)(t + e * NT) * W] = acc[bt][e];
     }
+  }
+}
+
+// ACC += part[0] + ... + part[G-2] over n4 groups of 4 floats (two complex
+// values), summed in group order
+__global__ void __launch_bounds__(256)
+k_acc_sum_parts(float4 *__restrict__ ACC, const float4 *__restrict__ part, int G, size_t n4) {
+  const size_t stride = (size_t)gridDim.x * 256;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += stride) {
+    float4 v = ACC[i];
+    for (int z = 1; z < G; ++z) {
+      const float4 u = part[(size_t)(z - 1) * n4 + i];
+      v = make_float4(v.x + u.x, v.y + u.y, v.z + u.z, v.w + u.w);
+    }
+    ACC[i] = v;
+  }
+}
+
+// ACC[b] = column IDFT(ACC[b] / Psi_hat), in place: every thread reads its
+// own column samples before the FFT.
+template <int N>
+__global__ void __launch_bounds__(CTile<N>::THREADS)
+k_cols_acc_finish(float2 *__restrict__ ACC, const float *__restrict__ psi, int W,
+                  const float2 *__restrict__ tw) {
+  constexpr int NT = CTile<N>::NT, M = CTile<N>::M, E = CTile<N>::E;
+  using PL = typename CTile<N>::PL;
+  __shared__ float2 lds[M * N];
+  const int m = threadIdx.x % M, t = threadIdx.x / M;
+  const int col = blockIdx.x * M + m;
+  const bool ok = col < W;
+  const int cc = ok ? col : 0;
+  const size_t plane = (size_t)N * W;
+  const int b = blockIdx.y;
+  float2 *accp = ACC + (size_t)b * plane + cc;
+  float2 v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = accp[(size_t)(t + e * NT) * W];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const float d = psi[(size_t)(t + e * NT) * W + cc];
+    v[e] = make_float2(v[e].x / d, v[e].y / d);
+  }
+  fft_line_p<PL, true>(v, t, LdsLine{lds + m, M}, tw);
+  if (ok) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) accp[(size_t)(t + e * NT) * W] = v[e];
   }
 }
 
@@ -726,6 +785,39 @@ hipError_t launch_cols_fft(const Sys2D &s, const float2 *A, float2 *F, int B, bo
   return hipGetLastError();
 }
 
+// Pair groups of a column pass whose grid (column tiles x image groups) has
+// `blocks` blocks: 1 when the grid fills the compute units, otherwise about
+// `per_cu` blocks per compute unit, at most `cap` groups, none of them empty.
+// The forward pass splits finer (its groups only re-read the spectrum); the
+// inverse pass adds one partial-sum plane per extra group.
+static int pair_groups(int blocks, int np, int num_cu, int per_cu, int cap) {
+  if (np <= 1 || blocks >= num_cu) return 1;
+  int g = (per_cu * num_cu + blocks - 1) / blocks;
+  g = g < np ? g : np;
+  g = g < cap ? g : cap;
+  const int per = (np + g - 1) / g;
+  return (np + per - 1) / per;
+}
+
+// images per block of the inverse accumulation: a single image does not
+// fill a BT = 2 block
+static int inv_bt(int nb) { return nb >= 2 ? kInvBT : 1; }
+
+int inv_pair_groups(const Sys2D &s, int nb, int np) {
+  if (SL_COL_V3_INV || !lines_supported(s.H)) return 1;
+  int M = 0;
+  switch (s.H) {
+#define X(N) \
+  case N:    \
+    M = CTile<N>::M; \
+    break;
+    SL_FOR_EACH_N(X)
+#undef X
+  }
+  const int bt = inv_bt(nb);
+  return pair_groups(((s.W + M - 1) / M) * ((nb + bt - 1) / bt), np, s.num_cu, 2, 16);
+}
+
 hipError_t launch_cols_filter_ifft(const Sys2D &s, const float2 *F, float2 *T, Chunk c,
                                    hipStream_t st) {
   switch (s.H) {
@@ -733,7 +825,9 @@ hipError_t launch_cols_filter_ifft(const Sys2D &s, const float2 *F, float2 *T, C
   case N:                                                                                    \
     if (SL_COL_V3_FWD)                                                                         \
       hipLaunchKernelGGL((k_cols_filter_ifft3<N, kFwdBT>),                                      \
-                         dim3((s.W + FTile<N>::M - 1) / FTile<N>::M, (c.nb + kFwdBT - 1) / kFwdBT), \
+                         dim3((s.W + FTile<N>::M - 1) / FTile<N>::M, (c.nb + kFwdBT - 1) / kFwdBT, \
+                              pair_groups(((s.W + FTile<N>::M - 1) / FTile<N>::M) *            \
+                                              ((c.nb + kFwdBT - 1) / kFwdBT), c.np, s.num_cu, 4, 32)), \
                          dim3(FTile<N>::THREADS), 0, st, F, s.filt, T, s.W, s.R, c.b0, c.nb, c.p0, \
                          c.np, s.twH);                                                         \
     else                                                                                       \
@@ -836,15 +930,50 @@ hipError_t launch_rows_thr(const Sys2D &s, float2 *T, float inv_n, Chunk c, cons
   return hipGetLastError();
 }
 
-hipError_t launch_cols_fft_acc(const Sys2D &s, const float2 *U, float2 *ACC, Chunk c, bool first,
-                               bool last, hipStream_t st) {
+hipError_t launch_cols_fft_acc(const Sys2D &s, const float2 *U, float2 *ACC, float2 *part,
+                               int G, int Btot, Chunk c, bool first, bool last, hipStream_t st) {
+  if (G < 1 || (G > 1 && (!part || SL_COL_V3_INV))) return hipErrorInvalidValue;
   switch (s.H) {
 #define X(N)                                                                                    \
   case N:                                                                                       \
-    hipLaunchKernelGGL((SL_COL_V3_INV ? k_cols_fft_acc3<N, kInvBT> : k_cols_fft_acc<N, kInvBT>), \
-                       col_grid<N>(s.W, (c.nb + kInvBT - 1) / kInvBT), \
-                       dim3(CTile<N>::THREADS), 0, st, U, s.filt, s.psi, ACC, s.W, s.R, c.b0,   \
-                       c.nb, c.p0, c.np, (int)first, (int)last, s.twH);                        \
+    if (SL_COL_V3_INV)                                                                          \
+      hipLaunchKernelGGL((k_cols_fft_acc3<N, kInvBT>), col_grid<N>(s.W, (c.nb + kInvBT - 1) / kInvBT), \
+                         dim3(CTile<N>::THREADS), 0, st, U, s.filt, s.psi, ACC, s.W, s.R, c.b0, \
+                         c.nb, c.p0, c.np, (int)first, (int)last, s.twH);                      \
+    else if (inv_bt(c.nb) == 1)                                                                 \
+      hipLaunchKernelGGL((k_cols_fft_acc<N, 1>),                                                \
+                         dim3((s.W + CTile<N>::M - 1) / CTile<N>::M, c.nb, G),                  \
+                         dim3(CTile<N>::THREADS), 0, st, U, s.filt, s.psi, ACC, part, Btot,     \
+                         s.W, s.R, c.b0, c.nb, c.p0, c.np, (int)first, (int)(last && G == 1),   \
+                         s.twH);                                                                \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_cols_fft_acc<N, kInvBT>),                                           \
+                         dim3((s.W + CTile<N>::M - 1) / CTile<N>::M, (c.nb + kInvBT - 1) / kInvBT, G), \
+                         dim3(CTile<N>::THREADS), 0, st, U, s.filt, s.psi, ACC, part, Btot,     \
+                         s.W, s.R, c.b0, c.nb, c.p0, c.np, (int)first, (int)(last && G == 1),   \
+                         s.twH);                                                                \
+    break;
+    SL_FOR_EACH_N(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cols_acc_finish(const Sys2D &s, float2 *ACC, const float2 *part, int G, int B,
+                                  hipStream_t st) {
+  // partial sums first, at full-device parallelism (a plane holds an even
+  // number of complex values: two per float4)
+  const size_t n4 = (size_t)B * s.H * s.W / 2;
+  const size_t want = (n4 + 255) / 256;
+  hipLaunchKernelGGL(k_acc_sum_parts, dim3((unsigned)(want < 8192 ? want : 8192)), dim3(256), 0,
+                     st, (float4 *)ACC, (const float4 *)part, G, n4);
+  switch (s.H) {
+#define X(N)                                                                                  \
+  case N:                                                                                     \
+    hipLaunchKernelGGL(k_cols_acc_finish<N>, col_grid<N>(s.W, B), dim3(CTile<N>::THREADS), 0, \
+                       st, ACC, s.psi, s.W, s.twH);                                           \
     break;
     SL_FOR_EACH_N(X)
 #undef X
