@@ -239,3 +239,48 @@ def inpainting_case(H, W, seed, kind):
     else:
         raise ValueError(kind)
     return clean, mask
+
+
+def _draw_segment(img, p, q, width):
+    """Set the pixels whose centre lies within width/2 of segment pq."""
+    H, W = img.shape
+    r = width / 2 + 1
+    y0, y1 = int(max(0, min(p[0], q[0]) - r)), int(min(H, max(p[0], q[0]) + r + 1))
+    x0, x1 = int(max(0, min(p[1], q[1]) - r)), int(min(W, max(p[1], q[1]) + r + 1))
+    if y1 <= y0 or x1 <= x0:
+        return
+    yy, xx = np.meshgrid(np.arange(y0, y1) + 0.5, np.arange(x0, x1) + 0.5, indexing="ij")
+    d = q - p
+    tt = np.clip(((yy - p[0]) * d[0] + (xx - p[1]) * d[1]) / max(d @ d, 1e-12), 0, 1)
+    dist2 = (yy - p[0] - tt * d[0]) ** 2 + (xx - p[1] - tt * d[1]) ** 2
+    img[y0:y1, x0:x1] |= dist2 <= (width / 2) ** 2
+
+
+def points_and_curves(H, W, seed):
+    """Binary test pair for image decomposition: (curves f0, points f1).
+
+    default_rng([seed, 6]): f0 holds U{4..8} cubic Bezier curves (control
+    points U over the image, 64 segments each, width U[m/256, m/128] with a
+    floor of 1.5 pixels, m = min(H, W)); f1 holds U{30..60} disks of radius
+    U[m/256, m/128] (floor 1.5 pixels) at uniform centres."""
+    rng = np.random.default_rng([seed, 6])
+    m = min(H, W)
+    curves = np.zeros((H, W), dtype=bool)
+    for _ in range(int(rng.integers(4, 9))):
+        ctl = rng.uniform([0, 0], [H, W], size=(4, 2))
+        width = max(1.5, rng.uniform(m / 256, m / 128))
+        s = np.linspace(0.0, 1.0, 65)[:, None]
+        pts = ((1 - s) ** 3 * ctl[0] + 3 * (1 - s) ** 2 * s * ctl[1] + 3 * (1 - s) * s ** 2 * ctl[2]
+               + s ** 3 * ctl[3])
+        for a in range(64):
+            _draw_segment(curves, pts[a], pts[a + 1], width)
+    points = np.zeros((H, W), dtype=bool)
+    yy, xx = np.meshgrid(np.arange(H) + 0.5, np.arange(W) + 0.5, indexing="ij")
+    for _ in range(int(rng.integers(30, 61))):
+        c = rng.uniform([0, 0], [H, W])
+        rad = max(1.5, rng.uniform(m / 256, m / 128))
+        y0, y1 = int(max(0, c[0] - rad - 1)), int(min(H, c[0] + rad + 2))
+        x0, x1 = int(max(0, c[1] - rad - 1)), int(min(W, c[1] + rad + 2))
+        sub = (yy[y0:y1, x0:x1] - c[0]) ** 2 + (xx[y0:y1, x0:x1] - c[1]) ** 2 <= rad ** 2
+        points[y0:y1, x0:x1] |= sub
+    return curves.astype(np.float64), points.astype(np.float64)
