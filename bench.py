@@ -216,7 +216,8 @@ def other_configs(reps=10):
 
 
 def inpainting_runs():
-    """Inpainting by iterative hard thresholding (Algorithm 3) at the paper's
+    """Inpainting by iterative hard thresholding (Algorithm 3) and image
+    decomposition (Algorithm 4).  Inpainting at the paper's
     settings, each run replayed from its HIP graph: one 512^2 image, R = 49,
     300 iterations, per mask type (random 80 %, squares 28 %, text-like
     strokes 25 %); a batch of 32 such images; one 192^3 video volume,
@@ -260,7 +261,27 @@ def inpainting_runs():
     out["batch_32x512_R49_300it"] = {"ms": round(ms, 2), "ms_per_iteration": round(ms / its, 4),
                                      "images_per_s": round(Bn / ms * 1e3, 2),
                                      "coefficients_per_s": Bn * s2.R * H * W * its / ms * 1e3}
-    del fm, mg, f, s2
+    del fm, mg, f
+    # image decomposition (Algorithm 4): 512^2 points-and-curves image, the
+    # shearlet systems SL2D_1 (shear levels [0, 0, 1, 1], R = 25) and SL2D_2
+    # ([1, 1, 2, 2], R = 49) each with the 4-scale wavelet bank (R = 13),
+    # 100 iterations, delta_init = 2, delta_min = 0.05
+    from paper_1402_5670_amd import metrics as Mt
+    curves, points = syn.points_and_curves(H, W, 900300)
+    fg = torch.from_numpy((curves + points)[None].astype(np.float32)).to(dev)
+    sw = Bd.System((H, W), J, wavelet=True)
+    dg = torch.full((1,), 2.0, device=dev)
+    dec = {}
+    for name, lv in (("SL2D_1", [0, 0, 1, 1]), ("SL2D_2", [1, 1, 2, 2])):
+        sd = s2 if list(lv) == list(levels) else Bd.System((H, W), J, lv)
+        f0, f1 = torch.empty_like(fg), torch.empty_like(fg)
+        ms = time_call(lambda: sd.decompose(sw, fg, dg, 0.05, 100, f0=f0, f1=f1, use_graph=True), 3)
+        dec[name] = {"R": sd.R, "ms_per_100_iterations": round(ms, 3),
+                     "q_opt_points": round(Mt.q_opt(points, f1[0].cpu().numpy())[0], 4),
+                     "q_opt_curves": round(Mt.q_opt(curves, f0[0].cpu().numpy())[0], 4)}
+    dec["paper_s_context"] = {"SL2D_1": 57.1, "SL2D_2": 87.8}
+    out["decomposition_512_100it"] = dec
+    del fg, sw, s2
     torch.cuda.empty_cache()
     dims, its3 = (192, 192, 192), 50
     clean = syn.moving_ellipses_video(*dims, 5000)

@@ -96,12 +96,29 @@ int sl_config_num_subbands(const sl_config *cfg, int *R_out);
 int sl_build_filters_host(const sl_config *cfg, double *filters_host,
                           double *dual_host, sl_subband *subbands_host);
 
+/* FP64 undecimated separable wavelet bank on the DFT grid (2D only): the 2D
+ * digital wavelet transform of Section 3.4 built from the QMF cascades of
+ * eq. lowhigh, without its subsampling (the stationary wavelet transform
+ * that Section 5's image decomposition pairs with the shearlets).  Subband
+ * order: lowpass h_J (x) h_J, then for j = 0..J-1 (coarse to fine) cone 1 =
+ * g_{J-j} along x1 times h_{J-j} along x2, cone 2 = h_{J-j} along x1 times
+ * g_{J-j} along x2, cone 3 = g_{J-j} along both; k1 = k2 = 0; R = 3 J + 1.
+ * Reads dims, n_scales, qmf and coeff_dtype of cfg (ndim must be 2); the
+ * shear levels, fan filter and full_system do not apply.  Outputs as for
+ * sl_build_filters_host.                                                    */
+int sl_build_wavelet_filters_host(const sl_config *cfg, double *filters_host,
+                                  double *dual_host, sl_subband *subbands_host);
+
 /* ---- system (host build + device upload) -------------------------------- */
 
 /* Build the filter bank on the host in FP64, round to FP32 and upload the
  * tables plus FFT twiddles (computed in FP64, rounded to FP32) to the
  * current HIP device.  *out is owned by the library.                        */
 int sl_build_system(const sl_config *cfg, sl_system **out);
+/* A system holding the wavelet bank of sl_build_wavelet_filters_host: every
+ * transform call accepts it like a 2D shearlet system (the pair packing,
+ * thresholds and dual-frame inverse only need real, even filters).         */
+int sl_build_wavelet_system(const sl_config *cfg, sl_system **out);
 void sl_free_system(sl_system *s);
 int sl_system_num_subbands(const sl_system *s, int *R_out);
 int sl_system_subband(const sl_system *s, int i, sl_subband *out);
@@ -183,6 +200,31 @@ int sl_inpaint(const sl_system *s, const float *f_masked_dev, const unsigned cha
                int batch, const float *delta_init_dev, double delta_min, int iterations,
                int t_begin, int t_end, float *f_dev, int use_graph, void *workspace_dev,
                size_t workspace_bytes, void *stream);
+
+/* Image decomposition by iterative thresholding with two transforms
+ * (Algorithm 4; Section 5, image decomposition).  From f0 = f1 = 0, iteration
+ * t = 0..iterations-1 computes, from the estimates of the iteration's start,
+ *   f_res = f - (f0 + f1)
+ *   f0 = T0^-1 T_delta_t T0 (f_res + f0)     (system s0, e.g. shearlets)
+ *   f1 = T1^-1 T_delta_t T1 (f_res + f1)     (system s1, e.g. wavelets)
+ * with f_res + f0 = f - f1 and f_res + f1 = f - f0 formed directly, T_delta
+ * and the schedule delta_t as in sl_inpaint (each system thresholds subband
+ * i at delta_t ||psi_i||_2 and keeps its lowpass).  s0 and s1 must have the
+ * same dims and device.
+ *   f_dev [B][dims] float32; delta_init_dev [B] float32;
+ *   f0_dev, f1_dev [B][dims] float32, distinct: on entry the estimates after
+ *     t_begin iterations (not read when t_begin = 0), on exit after t_end;
+ *   use_graph: as in sl_inpaint; the graphs are kept by s0, keyed by s1's
+ *     identity (a system built later never reuses them);
+ *   all buffers 16-byte aligned; workspace_dev of at least
+ *     sl_decompose_workspace_size(s0, s1, B) bytes.
+ * Errors as in sl_inpaint, plus SL_EINVAL for systems of different dims.   */
+int sl_decompose_workspace_size(const sl_system *s0, const sl_system *s1, int batch,
+                                size_t *bytes_out);
+int sl_decompose(const sl_system *s0, const sl_system *s1, const float *f_dev, int batch,
+                 const float *delta_init_dev, double delta_min, int iterations, int t_begin,
+                 int t_end, float *f0_dev, float *f1_dev, int use_graph, void *workspace_dev,
+                 size_t workspace_bytes, void *stream);
 
 /* Adjoint of sl_inverse: c_i = IDFT(psi_hat_i / Psi_hat .* DFT(r)) for every
  * subband, i.e. the forward transform with the dual filters of eq.

@@ -79,6 +79,16 @@ _SIGS = {
                     ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                     ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
                     ctypes.c_void_p], ctypes.c_int),
+    "sl_build_wavelet_system": ([ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_void_p)],
+                                ctypes.c_int),
+    "sl_build_wavelet_filters_host": ([ctypes.POINTER(Config), ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p], ctypes.c_int),
+    "sl_decompose_workspace_size": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "sl_decompose": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                      ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                      ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
     "sl_inverse_adjoint": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                             ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
     "sl_cnn_packed_bytes": ([ctypes.c_int], ctypes.c_size_t),
@@ -211,6 +221,18 @@ def build_filters_host(dims, n_scales, shear_levels, full_system=False, qmf=None
     return filt, dual, [(s.cone, s.j, s.k1, s.k2, s.l2norm, s.l1norm) for s in subs]
 
 
+def build_wavelet_filters_host(dims, n_scales, qmf=None):
+    """Host FP64 wavelet bank: (filters [3J+1, *dims], Psi_hat, subbands)."""
+    cfg = _Cfg(dims, n_scales, [0] * int(n_scales), False, "f32", qmf, None)
+    R = 3 * int(n_scales) + 1
+    filt = np.zeros((R, *dims), dtype=np.float64)
+    dual = np.zeros(dims, dtype=np.float64)
+    subs = (Subband * R)()
+    check(lib().sl_build_wavelet_filters_host(ctypes.byref(cfg.c), filt.ctypes.data,
+                                              dual.ctypes.data, ctypes.cast(subs, ctypes.c_void_p)))
+    return filt, dual, [(s.cone, s.j, s.k1, s.k2, s.l2norm, s.l1norm) for s in subs]
+
+
 def _ptr(t):
     return ctypes.c_void_p(0 if t is None else t.data_ptr())
 
@@ -223,15 +245,23 @@ def _stream():
 class System:
     """A shearlet system resident on the current HIP device."""
 
-    def __init__(self, dims, n_scales, shear_levels, full_system=False, dtype="f32", qmf=None,
-                 dir_filter=None):
+    def __init__(self, dims, n_scales, shear_levels=None, full_system=False, dtype="f32",
+                 qmf=None, dir_filter=None, wavelet=False):
+        """wavelet=True builds the undecimated separable wavelet bank
+        (sl_build_wavelet_system) instead; shear_levels do not apply."""
         self.dims = tuple(int(d) for d in dims)
         self.n_scales = int(n_scales)
+        if shear_levels is None:
+            if not wavelet:
+                raise ValueError("shear_levels is required for a shearlet system")
+            shear_levels = [0] * self.n_scales
         self.shear_levels = tuple(int(v) for v in shear_levels)
         self.dtype = dtype
+        self.wavelet = bool(wavelet)
         self._cfg = _Cfg(dims, n_scales, shear_levels, full_system, dtype, qmf, dir_filter)
         h = ctypes.c_void_p()
-        check(lib().sl_build_system(ctypes.byref(self._cfg.c), ctypes.byref(h)))
+        build = lib().sl_build_wavelet_system if wavelet else lib().sl_build_system
+        check(build(ctypes.byref(self._cfg.c), ctypes.byref(h)))
         self._h = h
         R = ctypes.c_int()
         check(lib().sl_system_num_subbands(h, ctypes.byref(R)))
@@ -348,6 +378,37 @@ class System:
                                      ctypes.cast(Kh, ctypes.c_void_p), _ptr(out), _ptr(ws),
                                      ws.numel(), _stream()))
         return out
+
+    def decompose_workspace_bytes(self, other, batch):
+        n = ctypes.c_size_t()
+        check(lib().sl_decompose_workspace_size(self._h, other._h, int(batch), ctypes.byref(n)))
+        return n.value
+
+    def decompose(self, other, f, delta_init, delta_min, iterations, t_begin=0, t_end=None,
+                  f0=None, f1=None, use_graph=False, workspace=None):
+        """Iterations t_begin..t_end-1 of image decomposition (sl_decompose)
+        with this system as T0 and `other` as T1.  Returns (f0, f1), updated
+        in place when given."""
+        import torch
+        self._check_x(f)
+        B = f.shape[0]
+        f0 = torch.empty_like(f) if f0 is None else f0
+        f1 = torch.empty_like(f) if f1 is None else f1
+        self._check_x(f0)
+        self._check_x(f1)
+        if workspace is None:
+            n = self.decompose_workspace_bytes(other, B)
+            key = ("decompose", id(other), str(f.device))
+            workspace = self._ws.get(key)
+            if workspace is None or workspace.numel() < n:
+                workspace = torch.empty(n, dtype=torch.uint8, device=f.device)
+                self._ws[key] = workspace
+        t_end = iterations if t_end is None else t_end
+        check(lib().sl_decompose(self._h, other._h, _ptr(f), B, _ptr(delta_init),
+                                 float(delta_min), int(iterations), int(t_begin), int(t_end),
+                                 _ptr(f0), _ptr(f1), 1 if use_graph else 0, _ptr(workspace),
+                                 workspace.numel(), _stream()))
+        return f0, f1
 
     def inpaint_workspace_bytes(self, batch):
         n = ctypes.c_size_t()

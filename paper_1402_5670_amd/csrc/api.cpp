@@ -2,11 +2,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <complex>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <mutex>
 #include <map>
 #include <string>
 #include <vector>
@@ -395,6 +398,85 @@ int inpaint_launches(const sl_system *s, const InpaintArgs &a, hipStream_t st) {
   return SL_OK;
 }
 
+
+// Run `launches` on st directly, or (use_graph) replay the graph cached on
+// `owner` under `key`, capturing and instantiating it on the first call.
+int run_or_replay(const sl_system *owner, const std::vector<uint64_t> &key, bool use_graph,
+                  hipStream_t st, const std::function<int(hipStream_t)> &launches) {
+  if (!use_graph) return launches(st);
+  auto *ms = const_cast<sl_system *>(owner);
+  std::lock_guard<std::mutex> lock(ms->graph_mu);
+  for (auto &gr : ms->graphs)
+    if (gr.key == key) {
+      SL_TRY(hipGraphLaunch(gr.exec, st));
+      return SL_OK;
+    }
+  // capture on a private stream, instantiate, keep
+  hipStream_t cs = nullptr;
+  SL_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return hip_fail(e, "hipStreamBeginCapture");
+  }
+  g_capturing = true;
+  int rc = launches(cs);
+  g_capturing = false;
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(cs, &graph);
+  (void)hipStreamDestroy(cs);
+  if (rc || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc ? rc : hip_fail(e, "hipStreamEndCapture");
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  if (ms->graphs.size() >= 4) {
+    (void)hipGraphExecDestroy(ms->graphs.front().exec);
+    (void)hipGraphDestroy(ms->graphs.front().graph);
+    ms->graphs.erase(ms->graphs.begin());
+  }
+  ms->graphs.push_back({key, graph, exec});
+  SL_TRY(hipGraphLaunch(exec, st));
+  return SL_OK;
+}
+
+// Decomposition workspace: the larger of the two systems' transform
+// workspaces (they run one after the other), then g0 and g1 [B][npix]
+// float32 and sigma [B].
+struct DecompLayout {
+  size_t off_g0, off_g1, off_sigma, total;
+};
+
+DecompLayout decomp_layout(const sl_system *s0, const sl_system *s1, int B) {
+  DecompLayout L;
+  const size_t plane = 4ull * (size_t)s0->cfg.npix() * B;
+  L.off_g0 = std::max(layout(s0, B).total, layout(s1, B).total);
+  L.off_g1 = align_up(L.off_g0 + plane);
+  L.off_sigma = align_up(L.off_g1 + plane);
+  L.total = align_up(L.off_sigma + 4ull * B);
+  return L;
+}
+
+sl::ThrArgs unit_thresholds(const sl_system *s, const float *sigma) {
+  sl::ThrArgs thr{};
+  thr.sigma = sigma;
+  thr.l2 = s->d_l2;
+  thr.jof = s->d_jof;
+  for (int j = 0; j < s->cfg.J; ++j) thr.K[j] = 1.0f;
+  return thr;
+}
+
+uint64_t bits_of(double v) {
+  uint64_t b;
+  std::memcpy(&b, &v, sizeof(b));
+  return b;
+}
+
 }  // namespace
 
 int sl::set_error(int code, const std::string &msg) { return fail(code, msg); }
@@ -438,23 +520,49 @@ int sl_build_filters_host(const sl_config *cfg, double *filters_host, double *du
   return SL_OK;
 }
 
-int sl_build_system(const sl_config *cfg, sl_system **out) {
+}  // extern "C"
+
+namespace {
+
+// The wavelet bank reads dims, n_scales, the QMF and the storage type of a
+// configuration; its shear levels and fan filter do not apply.
+int parse_wavelet_config(const sl_config *cfg, slh::Config &c, std::string &err) {
+  if (!cfg) {
+    err = "cfg is NULL";
+    return SL_EINVAL;
+  }
+  if (cfg->ndim != 2) {
+    err = "the wavelet bank is two-dimensional";
+    return SL_EINVAL;
+  }
+  sl_config w = *cfg;
+  std::vector<int> zeros(std::max(1, cfg->n_scales), 0);
+  w.shear_levels = zeros.data();
+  w.dir_filter = nullptr;
+  w.dir_rows = w.dir_cols = 0;
+  w.full_system = 0;
+  return slh::parse_config(&w, c, err);
+}
+
+int build_system_impl(const sl_config *cfg, bool wavelet, sl_system **out) {
   if (!out) return fail(SL_EINVAL, "out is NULL");
   *out = nullptr;
+  static std::atomic<uint64_t> next_serial{1};
   auto *s = new sl_system();
+  s->serial = next_serial++;
   std::string err;
-  int rc = slh::parse_config(cfg, s->cfg, err);
+  int rc = wavelet ? parse_wavelet_config(cfg, s->cfg, err) : slh::parse_config(cfg, s->cfg, err);
   if (rc != SL_OK) {
     delete s;
     return fail(rc, err);
   }
   const int64_t npix = s->cfg.npix();
   const bool is3d = s->cfg.ndim == 3;
-  int R = 0;
-  sl_config_num_subbands(cfg, &R);
+  const int R = wavelet ? 3 * s->cfg.J + 1 : (int)slh::enumerate_subbands(s->cfg).size();
   std::vector<double> filt64(is3d ? 0 : (size_t)R * npix);
   slh::Bank bank;
-  rc = slh::build_bank(s->cfg, bank, is3d ? nullptr : filt64.data(), err);
+  rc = wavelet ? slh::build_wavelet_bank(s->cfg, bank, filt64.data(), err)
+               : slh::build_bank(s->cfg, bank, is3d ? nullptr : filt64.data(), err);
   if (rc != SL_OK) {
     delete s;
     return fail(rc, err);
@@ -546,6 +654,42 @@ int sl_build_system(const sl_config *cfg, sl_system **out) {
     s->d_tw[N] = p;
   }
   *out = s;
+  return SL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sl_build_system(const sl_config *cfg, sl_system **out) {
+  return build_system_impl(cfg, false, out);
+}
+
+int sl_build_wavelet_system(const sl_config *cfg, sl_system **out) {
+  return build_system_impl(cfg, true, out);
+}
+
+int sl_build_wavelet_filters_host(const sl_config *cfg, double *filters_host, double *dual_host,
+                                  sl_subband *subbands_host) {
+  slh::Config c;
+  std::string err;
+  int rc = parse_wavelet_config(cfg, c, err);
+  if (rc != SL_OK) return fail(rc, err);
+  slh::Bank bank;
+  std::vector<double> tmp;
+  double *fo = filters_host;
+  if (!fo) {
+    tmp.resize((size_t)(3 * c.J + 1) * c.npix());
+    fo = tmp.data();
+  }
+  rc = slh::build_wavelet_bank(c, bank, fo, err);
+  if (dual_host) std::copy(bank.dual.begin(), bank.dual.end(), dual_host);
+  if (subbands_host)
+    for (size_t i = 0; i < bank.subbands.size(); ++i) {
+      const auto &b = bank.subbands[i];
+      subbands_host[i] = {b.cone, b.j, b.k1, b.k2, bank.l2[i], bank.l1[i]};
+    }
+  if (rc != SL_OK) return fail(rc, err);
   return SL_OK;
 }
 
@@ -728,55 +872,82 @@ int sl_inpaint(const sl_system *s, const float *f_masked_dev, const unsigned cha
   if (t_begin == t_end) return SL_OK;
   InpaintArgs a{f_masked_dev, mask_dev, batch,   delta_init_dev, delta_min,
                 iterations,   t_begin,  t_end,   f_dev,          (char *)workspace_dev};
-  hipStream_t st = (hipStream_t)stream;
-  if (!use_graph) return inpaint_launches(s, a, st);
+  std::vector<uint64_t> key = {0x1a, (uint64_t)(uintptr_t)f_masked_dev, (uint64_t)(uintptr_t)mask_dev,
+                               (uint64_t)batch, (uint64_t)(uintptr_t)delta_init_dev,
+                               bits_of(delta_min), (uint64_t)iterations, (uint64_t)t_begin,
+                               (uint64_t)t_end, (uint64_t)(uintptr_t)f_dev,
+                               (uint64_t)(uintptr_t)workspace_dev, (uint64_t)s->chunk_cap};
+  return run_or_replay(s, key, use_graph != 0, (hipStream_t)stream,
+                       [&](hipStream_t q) { return inpaint_launches(s, a, q); });
+}
 
-  auto *ms = const_cast<sl_system *>(s);
-  uint64_t dm_bits;
-  std::memcpy(&dm_bits, &delta_min, sizeof(dm_bits));
-  std::vector<uint64_t> key = {(uint64_t)(uintptr_t)f_masked_dev, (uint64_t)(uintptr_t)mask_dev,
-                               (uint64_t)batch, (uint64_t)(uintptr_t)delta_init_dev, dm_bits,
-                               (uint64_t)iterations, (uint64_t)t_begin, (uint64_t)t_end,
-                               (uint64_t)(uintptr_t)f_dev, (uint64_t)(uintptr_t)workspace_dev,
-                               (uint64_t)s->chunk_cap};
-  std::lock_guard<std::mutex> lock(ms->graph_mu);
-  for (auto &gr : ms->graphs)
-    if (gr.key == key) {
-      SL_TRY(hipGraphLaunch(gr.exec, st));
-      return SL_OK;
-    }
-  // capture the iterations on a private stream, instantiate, keep
-  hipStream_t cs = nullptr;
-  SL_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) {
-    (void)hipStreamDestroy(cs);
-    return hip_fail(e, "hipStreamBeginCapture");
-  }
-  g_capturing = true;
-  int rc = inpaint_launches(s, a, cs);
-  g_capturing = false;
-  hipGraph_t graph = nullptr;
-  e = hipStreamEndCapture(cs, &graph);
-  (void)hipStreamDestroy(cs);
-  if (rc || e != hipSuccess) {
-    if (graph) (void)hipGraphDestroy(graph);
-    return rc ? rc : hip_fail(e, "hipStreamEndCapture");
-  }
-  hipGraphExec_t exec = nullptr;
-  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  if (e != hipSuccess) {
-    (void)hipGraphDestroy(graph);
-    return hip_fail(e, "hipGraphInstantiate");
-  }
-  if (ms->graphs.size() >= 4) {
-    (void)hipGraphExecDestroy(ms->graphs.front().exec);
-    (void)hipGraphDestroy(ms->graphs.front().graph);
-    ms->graphs.erase(ms->graphs.begin());
-  }
-  ms->graphs.push_back({key, graph, exec});
-  SL_TRY(hipGraphLaunch(exec, st));
+int sl_decompose_workspace_size(const sl_system *s0, const sl_system *s1, int batch,
+                                size_t *bytes_out) {
+  if (!s0 || !s1 || !bytes_out) return fail(SL_EINVAL, "NULL argument");
+  if (batch < 1) return fail(SL_EINVAL, "batch must be >= 1");
+  if (s0->cfg.ndim != s1->cfg.ndim || s0->cfg.npix() != s1->cfg.npix())
+    return fail(SL_EINVAL, "the two systems must have the same dims");
+  *bytes_out = decomp_layout(s0, s1, batch).total;
   return SL_OK;
+}
+
+int sl_decompose(const sl_system *s0, const sl_system *s1, const float *f_dev, int batch,
+                 const float *delta_init_dev, double delta_min, int iterations, int t_begin,
+                 int t_end, float *f0_dev, float *f1_dev, int use_graph, void *workspace_dev,
+                 size_t workspace_bytes, void *stream) {
+  if (!s0 || !s1) return fail(SL_EINVAL, "system is NULL");
+  if (s0->cfg.ndim != s1->cfg.ndim)
+    return fail(SL_EINVAL, "the two systems must have the same dims");
+  for (int a = 0; a < s0->cfg.ndim; ++a)
+    if (s0->cfg.dims[a] != s1->cfg.dims[a])
+      return fail(SL_EINVAL, "the two systems must have the same dims");
+  if (s0->device != s1->device) return fail(SL_EINVAL, "the two systems are on different devices");
+  if (batch < 1 || batch > 65535) return fail(SL_EINVAL, "batch must be in 1..65535");
+  if (!f_dev || !delta_init_dev || !f0_dev || !f1_dev || !workspace_dev)
+    return fail(SL_EINVAL, "NULL buffer");
+  if (f0_dev == f1_dev) return fail(SL_EINVAL, "f0 and f1 must be different buffers");
+  if (iterations < 1) return fail(SL_EINVAL, "iterations must be >= 1");
+  if (t_begin < 0 || t_end < t_begin || t_end > iterations)
+    return fail(SL_EINVAL, "need 0 <= t_begin <= t_end <= iterations");
+  if (!(delta_min >= 0.0) || !std::isfinite(delta_min))
+    return fail(SL_EINVAL, "delta_min must be finite and >= 0");
+  if (((uintptr_t)f_dev | (uintptr_t)f0_dev | (uintptr_t)f1_dev | (uintptr_t)workspace_dev) & 15u)
+    return fail(SL_EINVAL, "f, f0, f1 and the workspace must be 16-byte aligned");
+  if (s0->cfg.J > sl::kMaxScales || s1->cfg.J > sl::kMaxScales)
+    return fail(SL_EUNSUPPORTED, "too many scales");
+  if (s0->cfg.npix() % 4) return fail(SL_EUNSUPPORTED, "the sample count must be a multiple of 4");
+  const DecompLayout L = decomp_layout(s0, s1, batch);
+  if (workspace_bytes < L.total)
+    return fail(SL_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != s0->device)
+    return fail(SL_EINVAL, "the current HIP device is not the systems' device");
+  if (t_begin == t_end) return SL_OK;
+  char *ws = (char *)workspace_dev;
+  float *g0 = (float *)(ws + L.off_g0), *g1 = (float *)(ws + L.off_g1);
+  float *sigma = (float *)(ws + L.off_sigma);
+  const sl::ThrArgs thr0 = unit_thresholds(s0, sigma), thr1 = unit_thresholds(s1, sigma);
+  const size_t n = (size_t)s0->cfg.npix() * batch;
+  auto launches = [&](hipStream_t q) -> int {
+    for (int t = t_begin; t < t_end; ++t) {
+      SL_LAUNCH(P_AUX, q,
+                sl::launch_decompose_mix(f_dev, f0_dev, f1_dev, g0, g1, n, t == 0, delta_init_dev,
+                                         schedule_factor(delta_min, iterations, t), sigma, batch,
+                                         q));
+      int rc = denoise_fused_run(s0, g0, batch, thr0, f0_dev, ws, q);
+      if (!rc) rc = denoise_fused_run(s1, g1, batch, thr1, f1_dev, ws, q);
+      if (rc) return rc;
+    }
+    return SL_OK;
+  };
+  // s1 by serial number: a later system at the same address is a new key
+  std::vector<uint64_t> key = {0x2b, s1->serial, (uint64_t)(uintptr_t)f_dev,
+                               (uint64_t)batch, (uint64_t)(uintptr_t)delta_init_dev,
+                               bits_of(delta_min), (uint64_t)iterations, (uint64_t)t_begin,
+                               (uint64_t)t_end, (uint64_t)(uintptr_t)f0_dev,
+                               (uint64_t)(uintptr_t)f1_dev, (uint64_t)(uintptr_t)workspace_dev,
+                               (uint64_t)s0->chunk_cap, (uint64_t)s1->chunk_cap};
+  return run_or_replay(s0, key, use_graph != 0, (hipStream_t)stream, launches);
 }
 
 int sl_timing_enable(int on) {

@@ -390,6 +390,61 @@ double spatial_l1_1d(const double *hat, int N) {
 
 }  // namespace
 
+int build_wavelet_bank(const Config &c, Bank &bank, double *filters_out, std::string &err) {
+  if (c.ndim != 2) {
+    err = "the wavelet bank is two-dimensional";
+    return SL_EINVAL;
+  }
+  const int N2 = (int)c.dims[0], N1 = (int)c.dims[1];
+  const int64_t npix = c.npix();
+  bank.subbands.clear();
+  bank.subbands.push_back({0, -1, 0, 0});
+  for (int j = 0; j < c.J; ++j)
+    for (int cone = 1; cone <= 3; ++cone) bank.subbands.push_back({cone, j, 0, 0});
+  const int R = (int)bank.subbands.size();
+  bank.l2.assign(R, 0.0);
+  bank.l1.assign(R, 0.0);
+  bank.dual.assign((size_t)npix, 0.0);
+  std::vector<double> a1(N1), a2(N2), b1(N1), b2(N2), plane((size_t)npix);
+  for (int i = 0; i < R; ++i) {
+    const Subband &sb = bank.subbands[i];
+    const int m = sb.cone == 0 ? c.J : c.J - sb.j;
+    // factor along x1 (a1) and along x2 (a2)
+    for (int x = 0; x < N1; ++x) {
+      const double h = h_casc(c.h, m, x, N1);
+      const double g = sb.cone == 0 ? 0.0 : g_casc(c.h, m, x, N1);
+      a1[x] = (sb.cone == 1 || sb.cone == 3) ? g : h;
+      b1[x] = h;
+    }
+    for (int y = 0; y < N2; ++y) {
+      const double h = h_casc(c.h, m, y, N2);
+      const double g = sb.cone == 0 ? 0.0 : g_casc(c.h, m, y, N2);
+      a2[y] = (sb.cone == 2 || sb.cone == 3) ? g : h;
+      b2[y] = h;
+    }
+    double ss = 0.0;
+    for (int y = 0; y < N2; ++y)
+      for (int x = 0; x < N1; ++x) {
+        const double v = a2[y] * a1[x];
+        plane[(size_t)y * N1 + x] = v;
+        ss += v * v;
+        bank.dual[(size_t)y * N1 + x] += v * v;
+      }
+    bank.l2[i] = std::sqrt(ss / (double)npix);
+    // separable: the l1 norm of the spatial filter is the product of the
+    // factors' l1 norms
+    bank.l1[i] = spatial_l1_1d(a1.data(), N1) * spatial_l1_1d(a2.data(), N2);
+    if (filters_out) std::copy(plane.begin(), plane.end(), filters_out + (size_t)i * npix);
+  }
+  bank.dual_min = *std::min_element(bank.dual.begin(), bank.dual.end());
+  bank.dual_max = *std::max_element(bank.dual.begin(), bank.dual.end());
+  if (!(bank.dual_min > 1e-6 * bank.dual_max)) {
+    err = "Psi_hat is not bounded away from zero (min/max < 1e-6)";
+    return SL_EILLCOND;
+  }
+  return SL_OK;
+}
+
 int build_bank(const Config &c, Bank &bank, double *filters_out, std::string &err) {
   bank.subbands = enumerate_subbands(c);
   const int R = (int)bank.subbands.size();

@@ -77,6 +77,13 @@ struct Bank {
 };
 int build_bank(const Config &c, Bank &bank, double *filters_out, std::string &err);
 
+// Undecimated separable wavelet bank (2D only) from the same QMF cascades
+// (eq. lowhigh; the 2D digital wavelet transform of Section 3.4 without its
+// subsampling): lowpass h_J (x) h_J, then for j = 0..J-1 cone 1 = g_{J-j}
+// along x1 times h_{J-j} along x2, cone 2 = the transpose, cone 3 =
+// g_{J-j} along both; k1 = k2 = 0.  R = 3 J + 1.
+int build_wavelet_bank(const Config &c, Bank &bank, double *filters_out, std::string &err);
+
 // 3D factor tables used by the device (and by build_bank).
 struct Tables3D {
   // per scale j: plane[(j, k, pair)] where pair indexes an ordered

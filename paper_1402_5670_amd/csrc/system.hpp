@@ -18,6 +18,7 @@ struct sl_system {
   int R = 0;
   int device = 0;
   int num_cu = 1;                 // compute units of the device
+  uint64_t serial = 0;            // unique per built system (graph cache keys)
   size_t chunk_cap = 0;
   float *d_filt = nullptr;    // 2D: [R][H][W]
   float *d_psi = nullptr;     // Psi_hat on the grid

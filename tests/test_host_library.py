@@ -140,3 +140,33 @@ def test_missing_library_fails_loudly(tmp_path):
                        timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "raised" in r.stdout
+
+
+@pytest.mark.parametrize("dims,J", [((64, 64), 3), ((24, 96), 2), ((16, 32), 1)])
+def test_wavelet_bank_matches_oracle(dims, J):
+    # the library's closed form of the undecimated wavelet bank against the
+    # oracle's spatial construction (cascades, tensor products, periodisation)
+    from oracle import decompose as D
+    _lib()
+    f, d, subs = B.build_wavelet_filters_host(dims, J)
+    o = D.build_wavelet_2d(dims, J)
+    assert np.max(np.abs(f - o.filters)) < 1e-12
+    assert np.max(np.abs(d - o.dual_weight)) < 1e-12
+    assert [(s.cone, s.j, s.k1, s.k2) for s in o.subbands] == [s[:4] for s in subs]
+    assert np.max(np.abs(np.array([s[4] for s in subs]) - o.l2norms())) < 1e-12
+    # l1 norms of the spatial filters (the FP16 scale bound)
+    N2, N1 = dims
+    per = np.stack([F.periodize2d(fl, N2, N1) for _, fl in D.spatial_wavelet_filters_2d(J)])
+    l1 = np.sum(np.abs(per), axis=(1, 2))
+    assert np.max(np.abs(np.array([s[5] for s in subs]) - l1) / l1) < 1e-10
+
+
+def test_wavelet_bank_errors():
+    _lib()
+    with pytest.raises(B.ShearletError) as e:
+        B.build_wavelet_filters_host((40, 40), 2)
+    assert e.value.code == -3
+    cfg = B.Config()
+    cfg.ndim = 3
+    cfg.n_scales = 1
+    assert _lib().sl_build_wavelet_filters_host(ctypes.byref(cfg), None, None, None) == -1
