@@ -43,20 +43,24 @@ def _gpu(x):
     return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(DEV)
 
 
-@pytest.mark.parametrize("dims,J,Bn", [((64, 64), 3, 2), ((24, 96), 2, 3), ((512, 512), 4, 1)])
-def test_wavelet_system_parity(dims, J, Bn):
-    print(f"case: wavelet system {dims} J={J} B={Bn}", flush=True)
+@pytest.mark.parametrize("dims,J,Bn,dtype,tol", [
+    ((64, 64), 3, 2, "f32", 1e-5), ((24, 96), 2, 3, "f32", 1e-5), ((512, 512), 4, 1, "f32", 1e-5),
+    ((128, 128), 3, 2, "f16", 2e-3), ((128, 128), 3, 2, "bf16", 2e-2)])
+def test_wavelet_system_parity(dims, J, Bn, dtype, tol):
+    print(f"case: wavelet system {dims} J={J} B={Bn} {dtype}", flush=True)
     x = np.random.default_rng(51).standard_normal((Bn, *dims))
-    sw = B.System(dims, J, wavelet=True)
+    sw = B.System(dims, J, wavelet=True, dtype=dtype)
     o = D.build_wavelet_2d(dims, J)
     assert sw.R == 3 * J + 1
-    c, _ = sw.forward(_gpu(x))
-    xr = sw.inverse(c)
+    c, sc = sw.forward(_gpu(x))
+    xr = sw.inverse(c, sc)
     torch.cuda.synchronize()
-    cg = c.cpu().numpy()
+    cg = c.float().cpu().numpy().astype(np.float64)
+    if dtype != "f32":
+        cg = cg * sc.cpu().numpy().astype(np.float64)[:, :, None, None]
     for b in range(Bn):
-        assert rel(cg[b], T.forward(x[b], o.filters)) < 1e-5
-    assert rel(xr.cpu().numpy(), x) < 1e-5
+        assert rel(cg[b], T.forward(x[b], o.filters)) < tol
+    assert rel(xr.cpu().numpy(), x) < tol
 
 
 def _sigma32(dinit, delta_min, iterations, t):
