@@ -110,6 +110,26 @@ def test_c2_batched_sampled_parity():
     assert torch.equal(c, c2)
 
 
+def test_largest_plane_sampled_parity():
+    # the largest supported plane, 1024 x 1024, J = 4, d = [1, 1, 2, 2] (R = 49),
+    # two images (two images per inverse block, one column group): every
+    # seventh subband against the oracle, the reconstruction in full
+    print("case: 2x1024x1024 J=4 d=[1,1,2,2]", flush=True)
+    Bn = 2
+    xs = np.stack([syn.noisy_cartoon2d(1024, 1024, 2100 + b, 0.1)[1] for b in range(Bn)])
+    sysg = B.System((1024, 1024), 4, [1, 1, 2, 2])
+    xg = _gpu(xs)
+    c, _ = sysg.forward(xg)
+    xr = sysg.inverse(c)
+    torch.cuda.synchronize()
+    o = S.build_2d((1024, 1024), 4, [1, 1, 2, 2])
+    for b in range(Bn):
+        for i in range(0, sysg.R, 7):
+            ref = T.forward_one(xs[b], o.filters[i])
+            assert rel(c[b, i].cpu().numpy(), ref) < 1e-5, (b, i)
+        assert rel(xr[b].cpu().numpy(), xs[b]) < 1e-5
+
+
 @pytest.mark.parametrize("dtype,tol", [("f16", 2e-3), ("bf16", 2e-2)])
 def test_half_storage(dtype, tol):
     print(f"case: 384x384 J=3 d=[1,1,2] storage {dtype}", flush=True)

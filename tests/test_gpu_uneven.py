@@ -100,8 +100,8 @@ def test_uneven_autotune(tmp_path):
 
 def test_c4_uneven_64_images():
     # 64 images, sizes drawn uniformly from {256, 384, 512, 1024}^2 (seed 4000), 3 scales
-    # [1, 1, 2] (R = 33), FP16 storage, autotuned and replayed from one graph; the oracle
-    # checks one image of every size class in full, the reconstruction every image
+    # [1, 1, 2] (R = 33), FP16 storage, autotuned and replayed from one graph; every
+    # image's coefficients and reconstruction against the FP64 oracle
     print("case: C4 uneven batch, 64 images", flush=True)
     sizes = syn.uneven_sizes(64, 4000)
     classes = sorted(set(sizes))
@@ -123,10 +123,21 @@ def test_c4_uneven_64_images():
     m.graph_build(3, xs, coeffs, scales, outs=outs, workspace=ws)
     m.graph_launch()
     torch.cuda.synchronize()
+    # every image: coefficients (FP16 storage) and reconstruction against the
+    # FP64 oracle, reported per image
+    worst = 0.0
     for s, imgs, c, sc, o in zip(systems, host, coeffs, scales, outs):
-        assert rel(o.cpu().numpy(), imgs) < 2e-3
         orc = S.build_2d(s.dims, J, LEVELS)
-        cd = c[0].float().cpu().numpy().astype(np.float64) * sc[0].cpu().numpy()[:, None, None]
-        err = rel(cd, T.forward(imgs[0], orc.filters))
-        print(f"size {s.dims[0]}: {imgs.shape[0]} images, coefficient relL2 {err:.2e}", flush=True)
-        assert err < 2e-3
+        og = o.cpu().numpy()
+        errs = []
+        for k in range(imgs.shape[0]):
+            cd = c[k].float().cpu().numpy().astype(np.float64) * sc[k].cpu().numpy()[:, None, None]
+            ec = rel(cd, T.forward(imgs[k], orc.filters))
+            er = rel(og[k], imgs[k])
+            errs.append((ec, er))
+            assert ec < 2e-3 and er < 2e-3, (s.dims, k, ec, er)
+        line = " ".join(f"{ec:.1e}/{er:.1e}" for ec, er in errs)
+        print(f"size {s.dims[0]}: {imgs.shape[0]} images, coefficient/reconstruction relL2: {line}",
+              flush=True)
+        worst = max(worst, max(max(e) for e in errs))
+    print(f"worst relL2 over the 64 images: {worst:.2e}", flush=True)
