@@ -239,6 +239,18 @@ int sl_inverse_adjoint(const sl_system *s, const float *r_dev, int batch, float 
 int sl_system_set_chunk_bytes(sl_system *s, size_t bytes);
 size_t sl_system_chunk_bytes(const sl_system *s);
 
+/* Column tile shape of a 2D system's passes (a schedule choice; results are
+ * the same up to float32 summation order):
+ *   inv_images  images per inverse-accumulation block: 0 = two, or one for
+ *               a single image (default); 1 or 2 forces that shape;
+ *   split_pairs 1 (default): when the column grid leaves compute units idle,
+ *               the subband-pair loop of the column passes is split over
+ *               blocks (the inverse then sums per-group partial planes, which
+ *               sl_workspace_size includes); 0 keeps one group.
+ * SL_EINVAL for other values.  Changing them can change sl_workspace_size. */
+int sl_system_set_block_shape(sl_system *s, int inv_images, int split_pairs);
+int sl_system_block_shape(const sl_system *s, int *inv_images, int *split_pairs);
+
 /* ---- uneven batches (several image sizes in one schedule) ----------------
  * A multi-batch groups n_classes size classes: class s has its own system
  * (not owned; must outlive the multi-batch) and counts[s] images stored
@@ -256,9 +268,13 @@ int sl_multi_run(sl_multi *m, int what, const float *const *x_dev, void *const *
                  float *const *scales_dev, const float *const *sigma_dev, const float *K_host,
                  float *const *out_dev, void *workspace_dev, size_t workspace_bytes,
                  void *stream);
-/* Times forward + inverse for each class at chunk sizes of 32..2048 MiB that
- * fit the class's current workspace slot and keeps the fastest (cached by
- * size, R, batch and storage type in the text file cache_path, if given).  */
+/* Times forward + inverse for each class over its schedule candidates and
+ * keeps the fastest: chunk sizes of 32..2048 MiB that fit the class's
+ * current workspace slot and, for 2D classes, the block shape of
+ * sl_system_set_block_shape (one or two images per inverse-accumulation
+ * block, pair-loop split on or off).  Cached by size, R, batch and storage
+ * type in the text file cache_path, if given (one line per class: key,
+ * chunk bytes, images per block, split).                                    */
 int sl_multi_autotune(sl_multi *m, const float *const *x_dev, void *const *coeffs_dev,
                       float *const *scales_dev, float *const *out_dev, void *workspace_dev,
                       size_t workspace_bytes, const char *cache_path, void *stream);

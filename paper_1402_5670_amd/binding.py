@@ -111,6 +111,9 @@ _SIGS = {
                             ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "sl_system_set_chunk_bytes": ([ctypes.c_void_p, ctypes.c_size_t], ctypes.c_int),
     "sl_system_chunk_bytes": ([ctypes.c_void_p], ctypes.c_size_t),
+    "sl_system_set_block_shape": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "sl_system_block_shape": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
+                               ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "sl_multi_create": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                          ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "sl_multi_free": ([ctypes.c_void_p], None),
@@ -409,6 +412,11 @@ class System:
                                  _ptr(f0), _ptr(f1), 1 if use_graph else 0, _ptr(workspace),
                                  workspace.numel(), _stream()))
         return f0, f1
+
+    def set_block_shape(self, inv_images=0, split_pairs=1):
+        """Schedule choice of the 2D column passes (sl_system_set_block_shape)."""
+        check(lib().sl_system_set_block_shape(self._h, int(inv_images), int(split_pairs)))
+        self._ws = {}
 
     def inpaint_workspace_bytes(self, batch):
         n = ctypes.c_size_t()

@@ -131,6 +131,8 @@ sl::Sys2D view2d(const sl_system *s, int H, int W, int nH, int nW) {
   v.psi = s->d_psi;
   v.l1 = s->d_l1;
   v.num_cu = s->num_cu;
+  v.inv_images = s->inv_images;
+  v.split_pairs = s->split_pairs;
   v.twH = nH ? s->d_tw.at(nH) : nullptr;
   v.twW = nW ? s->d_tw.at(nW) : nullptr;
   return v;
@@ -876,7 +878,8 @@ int sl_inpaint(const sl_system *s, const float *f_masked_dev, const unsigned cha
                                (uint64_t)batch, (uint64_t)(uintptr_t)delta_init_dev,
                                bits_of(delta_min), (uint64_t)iterations, (uint64_t)t_begin,
                                (uint64_t)t_end, (uint64_t)(uintptr_t)f_dev,
-                               (uint64_t)(uintptr_t)workspace_dev, (uint64_t)s->chunk_cap};
+                               (uint64_t)(uintptr_t)workspace_dev, (uint64_t)s->chunk_cap,
+                               (uint64_t)s->inv_images, (uint64_t)s->split_pairs};
   return run_or_replay(s, key, use_graph != 0, (hipStream_t)stream,
                        [&](hipStream_t q) { return inpaint_launches(s, a, q); });
 }
@@ -946,7 +949,9 @@ int sl_decompose(const sl_system *s0, const sl_system *s1, const float *f_dev, i
                                bits_of(delta_min), (uint64_t)iterations, (uint64_t)t_begin,
                                (uint64_t)t_end, (uint64_t)(uintptr_t)f0_dev,
                                (uint64_t)(uintptr_t)f1_dev, (uint64_t)(uintptr_t)workspace_dev,
-                               (uint64_t)s0->chunk_cap, (uint64_t)s1->chunk_cap};
+                               (uint64_t)s0->chunk_cap, (uint64_t)s1->chunk_cap,
+                               (uint64_t)s0->inv_images, (uint64_t)s0->split_pairs,
+                               (uint64_t)s1->inv_images, (uint64_t)s1->split_pairs};
   return run_or_replay(s0, key, use_graph != 0, (hipStream_t)stream, launches);
 }
 

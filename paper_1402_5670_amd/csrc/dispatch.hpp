@@ -22,6 +22,9 @@ struct ThrArgs {
 struct Sys2D {
   int H, W, R, dtype;
   int num_cu;               // compute units of the device (grid sizing)
+  int inv_images;           // images per inverse accumulation block: 0 = by
+                            // batch (2, or 1 for a single image), or 1 / 2
+  int split_pairs;          // 1: small grids split the pair loop over blocks
   const float *filt;        // [R][H][W]
   const float *psi;         // [H][W]  Psi_hat
   const float *l1;          // [R]

@@ -790,8 +790,9 @@ hipError_t launch_cols_fft(const Sys2D &s, const float2 *A, float2 *F, int B, bo
 // `per_cu` blocks per compute unit, at most `cap` groups, none of them empty.
 // The forward pass splits finer (its groups only re-read the spectrum); the
 // inverse pass adds one partial-sum plane per extra group.
-static int pair_groups(int blocks, int np, int num_cu, int per_cu, int cap) {
-  if (np <= 1 || blocks >= num_cu) return 1;
+static int pair_groups(const Sys2D &s, int blocks, int np, int per_cu, int cap) {
+  const int num_cu = s.num_cu;
+  if (!s.split_pairs || np <= 1 || blocks >= num_cu) return 1;
   int g = (per_cu * num_cu + blocks - 1) / blocks;
   g = g < np ? g : np;
   g = g < cap ? g : cap;
@@ -799,9 +800,12 @@ static int pair_groups(int blocks, int np, int num_cu, int per_cu, int cap) {
   return (np + per - 1) / per;
 }
 
-// images per block of the inverse accumulation: a single image does not
-// fill a BT = 2 block
-static int inv_bt(int nb) { return nb >= 2 ? kInvBT : 1; }
+// images per block of the inverse accumulation: the system's choice, else
+// two (one for a single image, which does not fill a two-image block)
+static int inv_bt(const Sys2D &s, int nb) {
+  if (s.inv_images == 1 || s.inv_images == kInvBT) return s.inv_images;
+  return nb >= 2 ? kInvBT : 1;
+}
 
 int inv_pair_groups(const Sys2D &s, int nb, int np) {
   if (SL_COL_V3_INV || !lines_supported(s.H)) return 1;
@@ -814,8 +818,8 @@ int inv_pair_groups(const Sys2D &s, int nb, int np) {
     SL_FOR_EACH_N(X)
 #undef X
   }
-  const int bt = inv_bt(nb);
-  return pair_groups(((s.W + M - 1) / M) * ((nb + bt - 1) / bt), np, s.num_cu, 2, 16);
+  const int bt = inv_bt(s, nb);
+  return pair_groups(s, ((s.W + M - 1) / M) * ((nb + bt - 1) / bt), np, 2, 16);
 }
 
 hipError_t launch_cols_filter_ifft(const Sys2D &s, const float2 *F, float2 *T, Chunk c,
@@ -826,8 +830,8 @@ hipError_t launch_cols_filter_ifft(const Sys2D &s, const float2 *F, float2 *T, C
     if (SL_COL_V3_FWD)                                                                         \
       hipLaunchKernelGGL((k_cols_filter_ifft3<N, kFwdBT>),                                      \
                          dim3((s.W + FTile<N>::M - 1) / FTile<N>::M, (c.nb + kFwdBT - 1) / kFwdBT, \
-                              pair_groups(((s.W + FTile<N>::M - 1) / FTile<N>::M) *            \
-                                              ((c.nb + kFwdBT - 1) / kFwdBT), c.np, s.num_cu, 4, 32)), \
+                              pair_groups(s, ((s.W + FTile<N>::M - 1) / FTile<N>::M) *         \
+                                                 ((c.nb + kFwdBT - 1) / kFwdBT), c.np, 4, 32)),   \
                          dim3(FTile<N>::THREADS), 0, st, F, s.filt, T, s.W, s.R, c.b0, c.nb, c.p0, \
                          c.np, s.twH);                                                         \
     else                                                                                       \
@@ -940,7 +944,7 @@ hipError_t launch_cols_fft_acc(const Sys2D &s, const float2 *U, float2 *ACC, flo
       hipLaunchKernelGGL((k_cols_fft_acc3<N, kInvBT>), col_grid<N>(s.W, (c.nb + kInvBT - 1) / kInvBT), \
                          dim3(CTile<N>::THREADS), 0, st, U, s.filt, s.psi, ACC, s.W, s.R, c.b0, \
                          c.nb, c.p0, c.np, (int)first, (int)last, s.twH);                      \
-    else if (inv_bt(c.nb) == 1)                                                                 \
+    else if (inv_bt(s, c.nb) == 1)                                                              \
       hipLaunchKernelGGL((k_cols_fft_acc<N, 1>),                                                \
                          dim3((s.W + CTile<N>::M - 1) / CTile<N>::M, c.nb, G),                  \
                          dim3(CTile<N>::THREADS), 0, st, U, s.filt, s.psi, ACC, part, Btot,     \

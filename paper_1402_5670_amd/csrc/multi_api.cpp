@@ -2,10 +2,13 @@
 // include/shearlet.h).  Each size class runs the batched passes of its own
 // system; the classes are independent, so a captured HIP graph forks one
 // branch per class and the GPU runs the branches concurrently.  An autotuner
-// picks each class's chunk size (the number of subband pairs per pass
-// launch, which trades launch count against Infinity Cache residency of the
-// intermediate) by timing the candidates on the caller's buffers; results
-// are cached in a small text file.
+// picks each class's schedule by timing the candidates on the caller's
+// buffers: the chunk size (the number of subband pairs per pass launch,
+// which trades launch count against Infinity Cache residency of the
+// intermediate) and, in 2D, the column tile shape of the inverse
+// accumulation (one or two images per block) and whether small grids split
+// the subband-pair loop over blocks.  Results are cached in a small text
+// file, one line per class: key, chunk bytes, images per block, split.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -80,21 +83,42 @@ std::string tune_key(const sl_system *s, int count) {
   return k.str();
 }
 
-std::map<std::string, size_t> load_cache(const char *path) {
-  std::map<std::string, size_t> c;
+struct Sched {
+  size_t chunk;
+  int inv_images, split;
+};
+
+std::map<std::string, Sched> load_cache(const char *path) {
+  std::map<std::string, Sched> c;
   if (!path) return c;
   std::ifstream f(path);
-  std::string key;
-  size_t v;
-  while (f >> key >> v) c[key] = v;
+  std::string line;
+  while (std::getline(f, line)) {
+    std::istringstream ls(line);
+    std::string key;
+    Sched v{0, 0, 1};
+    if (!(ls >> key >> v.chunk)) continue;
+    if (!(ls >> v.inv_images >> v.split)) v.inv_images = 0, v.split = 1;
+    c[key] = v;
+  }
   return c;
 }
 
-void save_cache(const char *path, const std::map<std::string, size_t> &c) {
+void save_cache(const char *path, const std::map<std::string, Sched> &c) {
   if (!path) return;
   std::ofstream f(path);
-  for (auto &kv : c) f << kv.first << " " << kv.second << "\n";
+  for (auto &kv : c)
+    f << kv.first << " " << kv.second.chunk << " " << kv.second.inv_images << " "
+      << kv.second.split << "\n";
 }
+
+void apply(sl_system *s, const Sched &v) {
+  s->chunk_cap = v.chunk;
+  s->inv_images = v.inv_images;
+  s->split_pairs = v.split;
+}
+
+Sched current(const sl_system *s) { return {s->chunk_cap, s->inv_images, s->split_pairs}; }
 
 #define CK(expr)                                            \
   do {                                                      \
@@ -113,6 +137,21 @@ int sl_system_set_chunk_bytes(sl_system *s, size_t bytes) {
 }
 
 size_t sl_system_chunk_bytes(const sl_system *s) { return s ? s->chunk_cap : 0; }
+
+int sl_system_set_block_shape(sl_system *s, int inv_images, int split_pairs) {
+  if (!s || inv_images < 0 || inv_images > 2 || (split_pairs != 0 && split_pairs != 1))
+    return sl::set_error(SL_EINVAL, "inv_images must be 0, 1 or 2 and split_pairs 0 or 1");
+  s->inv_images = inv_images;
+  s->split_pairs = split_pairs;
+  return SL_OK;
+}
+
+int sl_system_block_shape(const sl_system *s, int *inv_images, int *split_pairs) {
+  if (!s || !inv_images || !split_pairs) return sl::set_error(SL_EINVAL, "NULL argument");
+  *inv_images = s->inv_images;
+  *split_pairs = s->split_pairs;
+  return SL_OK;
+}
 
 int sl_multi_create(sl_system *const *systems, const int *counts, int n_classes, sl_multi **out) {
   if (!systems || !counts || !out || n_classes < 1 || n_classes > 64)
@@ -171,6 +210,7 @@ int sl_multi_autotune(sl_multi *m, const float *const *x_dev, void *const *coeff
   hipStream_t st = (hipStream_t)stream;
   auto cache = load_cache(cache_path);
   static const size_t cand_mb[] = {32, 128, 512, 2048};
+  static const int cand_images[] = {1, 2}, cand_split[] = {1, 0};
   Bufs b{x_dev, coeffs_dev, scales_dev, nullptr, nullptr, out_dev, (char *)workspace_dev};
   hipEvent_t e0, e1;
   CK(hipEventCreate(&e0));
@@ -182,38 +222,45 @@ int sl_multi_autotune(sl_multi *m, const float *const *x_dev, void *const *coeff
   int rc = SL_OK;
   for (size_t s = 0; s < m->sys.size() && rc == SL_OK; ++s) {
     const std::string key = tune_key(m->sys[s], m->counts[s]);
+    sl_system *sy = m->sys[s];
     auto it = cache.find(key);
     if (it != cache.end()) {
-      size_t keep = m->sys[s]->chunk_cap;
-      m->sys[s]->chunk_cap = it->second;
+      const Sched keep = current(sy);
+      apply(sy, it->second);
       size_t need = 0;
-      sl_workspace_size(m->sys[s], m->counts[s], &need);
-      if (need > slot[s]) m->sys[s]->chunk_cap = keep;
+      sl_workspace_size(sy, m->counts[s], &need);
+      if (need > slot[s]) apply(sy, keep);
       continue;
     }
     float best = 1e30f;
-    size_t best_cap = m->sys[s]->chunk_cap;
-    for (size_t mb : cand_mb) {
-      m->sys[s]->chunk_cap = mb << 20;
-      size_t need = 0;
-      sl_workspace_size(m->sys[s], m->counts[s], &need);
-      if (need > slot[s]) continue;
-      rc = run_class(m, (int)s, b, 3, st);                       // warm-up
-      if (rc) break;
-      (void)hipEventRecord(e0, st);
-      for (int r = 0; r < 3 && rc == SL_OK; ++r) rc = run_class(m, (int)s, b, 3, st);
-      (void)hipEventRecord(e1, st);
-      if (rc) break;
-      (void)hipEventSynchronize(e1);
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (ms < best) {
-        best = ms;
-        best_cap = mb << 20;
-      }
-    }
-    m->sys[s]->chunk_cap = best_cap;
-    cache[key] = best_cap;
+    Sched best_s = current(sy);
+    // the block shape only applies to 2D systems
+    const int n_images = sy->cfg.ndim == 2 ? 2 : 1, n_split = sy->cfg.ndim == 2 ? 2 : 1;
+    for (size_t mb : cand_mb)
+      for (int ii = 0; ii < n_images && rc == SL_OK; ++ii)
+        for (int si = 0; si < n_split && rc == SL_OK; ++si) {
+          const Sched cand{mb << 20, sy->cfg.ndim == 2 ? cand_images[ii] : sy->inv_images,
+                           sy->cfg.ndim == 2 ? cand_split[si] : sy->split_pairs};
+          apply(sy, cand);
+          size_t need = 0;
+          sl_workspace_size(sy, m->counts[s], &need);
+          if (need > slot[s]) continue;
+          rc = run_class(m, (int)s, b, 3, st);                   // warm-up
+          if (rc) break;
+          (void)hipEventRecord(e0, st);
+          for (int r = 0; r < 3 && rc == SL_OK; ++r) rc = run_class(m, (int)s, b, 3, st);
+          (void)hipEventRecord(e1, st);
+          if (rc) break;
+          (void)hipEventSynchronize(e1);
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          if (ms < best) {
+            best = ms;
+            best_s = cand;
+          }
+        }
+    apply(sy, best_s);
+    cache[key] = best_s;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

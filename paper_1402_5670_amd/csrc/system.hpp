@@ -20,6 +20,8 @@ struct sl_system {
   int num_cu = 1;                 // compute units of the device
   uint64_t serial = 0;            // unique per built system (graph cache keys)
   size_t chunk_cap = 0;
+  int inv_images = 0;             // images per inverse accumulation block (0 = auto)
+  int split_pairs = 1;            // small grids split the pair loop over blocks
   float *d_filt = nullptr;    // 2D: [R][H][W]
   float *d_psi = nullptr;     // Psi_hat on the grid
   float *d_l2 = nullptr, *d_l1 = nullptr;

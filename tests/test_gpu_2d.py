@@ -110,6 +110,32 @@ def test_c2_batched_sampled_parity():
     assert torch.equal(c, c2)
 
 
+def test_block_shapes_agree():
+    # the schedule choices of the column passes change the float32 summation
+    # order only: every shape matches the oracle and the others
+    print("case: 3x256x256 J=3 d=[1,1,2] block shapes", flush=True)
+    Bn = 3
+    xs = np.stack([syn.noisy_cartoon2d(256, 256, 300 + b, 0.1)[1] for b in range(Bn)])
+    o = S.build_2d((256, 256), 3, [1, 1, 2])
+    sysg = B.System((256, 256), 3, [1, 1, 2])
+    xg = _gpu(xs)
+    outs = []
+    for shape in ((0, 1), (1, 1), (2, 1), (1, 0), (2, 0)):
+        sysg.set_block_shape(*shape)
+        c, _ = sysg.forward(xg)
+        xr = sysg.inverse(c)
+        torch.cuda.synchronize()
+        cg = c.cpu().numpy()
+        for b in range(Bn):
+            assert rel(cg[b], T.forward(xs[b], o.filters)) < 1e-5, shape
+        outs.append(xr.cpu().numpy())
+        assert rel(outs[-1], xs) < 1e-5, shape
+    for r in outs[1:]:
+        assert rel(r, outs[0]) < 1e-6
+    with pytest.raises(B.ShearletError):
+        sysg.set_block_shape(3, 1)
+
+
 def test_largest_plane_sampled_parity():
     # the largest supported plane, 1024 x 1024, J = 4, d = [1, 1, 2, 2] (R = 49),
     # two images (two images per inverse block, one column group): every

@@ -89,8 +89,12 @@ def test_uneven_autotune(tmp_path):
     cache = str(tmp_path / "tune.txt")
     m.autotune(xs, coeffs, scales, outs, ws, cache_path=cache)
     assert os.path.exists(cache)
-    lines = open(cache).read().split("\n")
-    assert len([ln for ln in lines if ln.strip()]) == len(SIZES)
+    lines = [ln.split() for ln in open(cache).read().split("\n") if ln.strip()]
+    assert len(lines) == len(SIZES)
+    # key, chunk bytes, images per inverse block (1 or 2), pair-loop split (0 or 1)
+    for ln in lines:
+        assert len(ln) == 4 and int(ln[1]) >= 1 << 20
+        assert int(ln[2]) in (1, 2) and int(ln[3]) in (0, 1)
     m.run(3, xs, coeffs, scales, outs=outs, workspace=ws)
     torch.cuda.synchronize()
     _check(systems, host, coeffs, scales, outs, 2e-3)
