@@ -391,8 +391,17 @@ def main():
                 "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(alu_frac, 4),
                 "peak_without_packed_fp32": FP32_VECTOR_PEAK_TFLOPS / 2,
                 "frac_without_packed_fp32": round(2 * alu_frac, 4)}
+    mt = measured_traffic(dom)
     roof.update({"kernel": dom, "avg_launch_us": round(d["avg_launch_us"], 2),
-                 "launches_per_step": launches, "traffic": measured_traffic(dom)})
+                 "launches_per_step": launches,
+                 # HBM bytes per launch from the copy-calibrated counters
+                 # (FETCH_SIZE + WRITE_SIZE), null if the kernels changed since
+                 "traffic": round(mt["bytes"]) if mt else None})
+    if mt:
+        roof.update({"traffic_unit": "bytes per launch",
+                     "traffic_read_bytes": round(mt["read_bytes"]),
+                     "traffic_write_bytes": round(mt["write_bytes"]),
+                     "traffic_kernel": mt["kernel"]})
 
     step_bytes = sum(pass_work(n, 0, H, W, R, Bn)[0] for n in rep)
     psnr_noisy = float(np.mean([psnr(pairs[b][0], pairs[b][1]) for b in range(Bn)]))
