@@ -249,6 +249,9 @@ int forward3d(const sl_system *s, const float *x, int batch, void *coef, float *
   const sl::Sys2D vr = view2d(s, D * H, W, 0, W);       // x lines
   const sl::Sys2D vy = view2d(s, H, W, H, 0);           // y lines per z-slice
   const sl::Sys2D vz = view2d(s, D, H * W, D, 0);       // z lines per volume
+  const sl::Sys2D vp = view2d(s, H, W, H, W);           // z-slices in LDS
+  const bool plane = s->plane3d && sl::plane_supported(H, W);
+  const float inv_vol = 1.0f / ((float)(D * H) * (float)W);
   const sl::Sys3D v3 = view3d(s);
   if (scaled) SL_LAUNCH(P_AUX, st, sl::launch_zero_u32(xmax, batch, st));
   SL_LAUNCH(P_ROWS_REAL_FFT, st, sl::launch_rows_real_fft(vr, x, F, scaled ? xmax : nullptr, batch, st));
@@ -263,8 +266,12 @@ int forward3d(const sl_system *s, const float *x, int batch, void *coef, float *
     for (int p0 = 0; p0 < P; p0 += np) {
       sl::Chunk c{b0, std::min(nb, batch - b0), p0, std::min(np, P - p0)};
       SL_LAUNCH(P_COLS_FILTER_IFFT, st, sl::launch_z_filter_ifft(v3, F, T, c, st));
-      SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, T, T, c.nb * c.np * D, true, st));
-      SL_LAUNCH(P_ROWS_COEF, st, sl::launch_rows_coef(vr, T, coef, scales, c, st));
+      if (plane) {
+        SL_LAUNCH(P_ROWS_COEF, st, sl::launch_plane_coef(vp, D, T, coef, scales, c, inv_vol, st));
+      } else {
+        SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, T, T, c.nb * c.np * D, true, st));
+        SL_LAUNCH(P_ROWS_COEF, st, sl::launch_rows_coef(vr, T, coef, scales, c, st));
+      }
     }
   return SL_OK;
 }
@@ -274,6 +281,8 @@ int inverse3d(const sl_system *s, const void *coef, const float *scales, int bat
   const int D = (int)s->cfg.dims[0], H = (int)s->cfg.dims[1], W = (int)s->cfg.dims[2];
   const sl::Sys2D vr = view2d(s, D * H, W, 0, W);
   const sl::Sys2D vy = view2d(s, H, W, H, 0);
+  const sl::Sys2D vp = view2d(s, H, W, H, W);
+  const bool plane = s->plane3d && sl::plane_supported(H, W);
   const sl::Sys3D v3 = view3d(s);
   int nb, np;
   chunk_plan(s, batch, nb, np);
@@ -281,8 +290,12 @@ int inverse3d(const sl_system *s, const void *coef, const float *scales, int bat
   for (int b0 = 0; b0 < batch; b0 += nb)
     for (int p0 = 0; p0 < P; p0 += np) {
       sl::Chunk c{b0, std::min(nb, batch - b0), p0, std::min(np, P - p0)};
-      SL_LAUNCH(P_ROWS_COEF_FFT, st, sl::launch_rows_coef_fft(vr, coef, scales, U, c, thr, st));
-      SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, U, U, c.nb * c.np * D, false, st));
+      if (plane) {
+        SL_LAUNCH(P_ROWS_COEF_FFT, st, sl::launch_plane_coef_fft(vp, D, coef, scales, U, c, thr, st));
+      } else {
+        SL_LAUNCH(P_ROWS_COEF_FFT, st, sl::launch_rows_coef_fft(vr, coef, scales, U, c, thr, st));
+        SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, U, U, c.nb * c.np * D, false, st));
+      }
       SL_LAUNCH(P_COLS_FFT_ACC, st,
                 sl::launch_z_fft_acc(v3, U, ACC, c, p0 == 0, p0 + c.np == P, st));
     }
@@ -310,6 +323,8 @@ int denoise_fused_run(const sl_system *s, const float *x_dev, int batch, const s
     const sl::Sys2D vr = view2d(s, D * H, W, 0, W);
     const sl::Sys2D vy = view2d(s, H, W, H, 0);
     const sl::Sys2D vz = view2d(s, D, H * W, D, 0);
+    const sl::Sys2D vp = view2d(s, H, W, H, W);
+    const bool plane = s->plane3d && sl::plane_supported(H, W);
     const sl::Sys3D v3 = view3d(s);
     SL_LAUNCH(P_ROWS_REAL_FFT, st, sl::launch_rows_real_fft(vr, x_dev, F, nullptr, batch, st));
     SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, F, F, batch * D, false, st));
@@ -318,9 +333,13 @@ int denoise_fused_run(const sl_system *s, const float *x_dev, int batch, const s
       for (int p0 = 0; p0 < P; p0 += np) {
         sl::Chunk c{b0, std::min(nb, batch - b0), p0, std::min(np, P - p0)};
         SL_LAUNCH(P_COLS_FILTER_IFFT, st, sl::launch_z_filter_ifft(v3, F, T, c, st));
-        SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, T, T, c.nb * c.np * D, true, st));
-        SL_LAUNCH(P_ROWS_THR, st, sl::launch_rows_thr(vr, T, inv_n, c, thr, st));
-        SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, T, T, c.nb * c.np * D, false, st));
+        if (plane) {
+          SL_LAUNCH(P_ROWS_THR, st, sl::launch_plane_thr(vp, D, T, inv_n, c, thr, st));
+        } else {
+          SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, T, T, c.nb * c.np * D, true, st));
+          SL_LAUNCH(P_ROWS_THR, st, sl::launch_rows_thr(vr, T, inv_n, c, thr, st));
+          SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, T, T, c.nb * c.np * D, false, st));
+        }
         SL_LAUNCH(P_COLS_FFT_ACC, st,
                   sl::launch_z_fft_acc(v3, T, ACC, c, p0 == 0, p0 + c.np == P, st));
       }
@@ -585,6 +604,10 @@ int build_system_impl(const sl_config *cfg, bool wavelet, sl_system **out) {
   // default 2 GiB: on MI355X larger chunks (fewer launches, no repeated
   // accumulator round trips) measured faster than Infinity-Cache-sized ones
   s->chunk_cap = (size_t)(cap_env ? std::max(1, std::atoi(cap_env)) : 2048) << 20;
+  // volumes: y and x passes of a z-slice in LDS where the slice fits
+  // ($SL_PLANE3D=0 keeps the separate line passes)
+  const char *plane_env = std::getenv("SL_PLANE3D");
+  s->plane3d = plane_env ? std::atoi(plane_env) != 0 : true;
   std::vector<float> f32(filt64.size());
   for (size_t i = 0; i < f32.size(); ++i) f32[i] = (float)filt64[i];
   std::vector<float> psi32(bank.dual.size());

@@ -98,6 +98,21 @@ struct Sys3D {
 
 hipError_t launch_z_filter_ifft(const Sys3D &s, const float2 *F, float2 *T, Chunk c,
                                 hipStream_t st);
+
+// Plane passes: the y and x line FFTs of each z-slice of a chunk's pair
+// volumes in LDS (s: the slice view, H x W with twiddles of both lengths;
+// D slices per volume).  plane_supported(H, W) tells which slice shapes
+// have them.  Results equal the separate line passes bit for bit.
+bool plane_supported(int H, int W);
+// T (after the z IDFT) -> y IDFT -> x IDFT -> coefficients (as rows_coef)
+hipError_t launch_plane_coef(const Sys2D &s, int D, const float2 *T, void *coef,
+                             const float *scales, Chunk c, float inv_n, hipStream_t st);
+// coefficients (decode, threshold) -> x DFT -> y DFT -> U (for z_fft_acc)
+hipError_t launch_plane_coef_fft(const Sys2D &s, int D, const void *coef, const float *scales,
+                                 float2 *U, Chunk c, const ThrArgs &thr, hipStream_t st);
+// T -> y IDFT, x IDFT, scale, threshold, x DFT, y DFT -> T (fused denoise)
+hipError_t launch_plane_thr(const Sys2D &s, int D, float2 *T, float inv_n, Chunk c,
+                            const ThrArgs &thr, hipStream_t st);
 hipError_t launch_z_fft_acc(const Sys3D &s, const float2 *U, float2 *ACC, Chunk c, bool first,
                             bool last, hipStream_t st);
 

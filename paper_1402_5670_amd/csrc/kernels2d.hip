@@ -726,6 +726,229 @@ k_rows_real_ifft(const float2 *__restrict__ V, float *__restrict__ x, int H, flo
 // ---------------------------------------------------------------------------
 // launchers: runtime length -> template instance
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Plane passes of a volume: the y and x line FFTs of one z-slice of a pair
+// volume in LDS (the slice, rows padded as the row kernels pad them), so the
+// slice crosses HBM once instead of once per axis.  They run the same plans
+// and line FFTs as the y column pass (k_cols_fft) and the x row passes
+// (k_rows_coef, k_rows_coef_fft, k_rows_thr), on the same values, so results
+// are bitwise those of the separate passes.  Slices of H x W with
+// H * row_lds_len(W) * 8 bytes of LDS (128 x 128: 144 KiB).
+// ---------------------------------------------------------------------------
+template <int H, int W>
+struct PlaneTile {
+  static constexpr int RL = row_lds_len<W>();
+  using PC = typename CTile<H>::PL;   // the y pass's plan
+  static constexpr int NTC = PC::NT, EC = PC::E;
+  static constexpr int NTR = Plan<W>::NT, ER = Plan<W>::E;
+  static constexpr int mn(int a, int b) { return a < b ? a : b; }
+  // threads: every column (row) of a pass has its own NTC (NTR) threads
+  static constexpr int THREADS = mn(1024, mn(NTC * W, NTR * H));
+  static constexpr int MC = THREADS / NTC, MR = THREADS / NTR;
+  static constexpr size_t LDS = (size_t)H * RL * sizeof(float2);
+  static constexpr bool OK = LDS <= 150 * 1024 && THREADS % 64 == 0 && W % MC == 0 &&
+                             H % MR == 0 && THREADS % NTC == 0 && THREADS % NTR == 0;
+};
+
+template <int H, int W>
+__device__ __forceinline__ LdsLine plane_col(float2 *pl, int x) {
+  return LdsLine{pl + x + (x >> 3), PlaneTile<H, W>::RL};
+}
+template <int H, int W>
+__device__ __forceinline__ LdsLine plane_row(float2 *pl, int y) {
+  return LdsLine{pl + y * PlaneTile<H, W>::RL, 0};
+}
+
+// y-line FFT of every column of the slice in LDS, in place
+template <int H, int W, bool INV>
+__device__ __forceinline__ void plane_cols(float2 *pl, const float2 *__restrict__ twH) {
+  using PT = PlaneTile<H, W>;
+  const int m = threadIdx.x % PT::MC, t = threadIdx.x / PT::MC;
+#pragma unroll 1
+  for (int c0 = 0; c0 < W; c0 += PT::MC) {
+    const LdsLine col = plane_col<H, W>(pl, c0 + m);
+    float2 v[PT::EC];
+#pragma unroll
+    for (int e = 0; e < PT::EC; ++e) v[e] = col[t + e * PT::NTC];
+    fft_line_p<typename PT::PC, INV>(v, t, col, twH);
+    __syncthreads();   // every read of the last exchange precedes the write-back
+#pragma unroll
+    for (int e = 0; e < PT::EC; ++e) col[t + e * PT::NTC] = v[e];
+  }
+  __syncthreads();
+}
+
+// forward: z-IDFT'd slice -> y IDFT -> x IDFT -> coefficients of the pair.
+// One block per (z-slice, pair, image); the slice's plane fills most of a
+// CU's LDS.  (A persistent variant that fetched the next slice into
+// registers during the transforms spilled at 128 x 128 and was slower.)
+template <int H, int W, int DT>
+__global__ void __launch_bounds__((PlaneTile<H, W>::THREADS))
+k_plane_coef(const float2 *__restrict__ T, typename Store<DT>::T *__restrict__ coef,
+             const float *__restrict__ scales, int D, int R, int b0, int p0, int np,
+             float inv_n, const float2 *__restrict__ twH, const float2 *__restrict__ twW) {
+  using PT = PlaneTile<H, W>;
+  __shared__ float2 pl[H * PT::RL];
+  const int z = blockIdx.x, pp = blockIdx.y, bl = blockIdx.z, b = b0 + bl;
+  const int ia = 2 * (p0 + pp), ib = ia + 1;
+  const size_t slice = (size_t)H * W, vol = slice * D;
+  const float2 *Ts = T + ((size_t)bl * np + pp) * vol + (size_t)z * slice;
+  for (int k = threadIdx.x; k < H * W; k += PT::THREADS) {
+    const int y = k / W, x = k % W;
+    pl[y * PT::RL + x + (x >> 3)] = Ts[k];
+  }
+  __syncthreads();
+  plane_cols<H, W, true>(pl, twH);
+  float sa = inv_n, sb = inv_n;
+  if (DT != 0) {
+    sa = inv_n / scales[(size_t)b * R + ia];
+    if (ib < R) sb = inv_n / scales[(size_t)b * R + ib];
+  }
+  using Raw = typename Store<DT>::Raw;
+  Raw *ca = (Raw *)(coef + ((size_t)b * R + ia) * vol + (size_t)z * slice);
+  Raw *cb = (Raw *)(coef + ((size_t)b * R + (ib < R ? ib : ia)) * vol + (size_t)z * slice);
+  const int t = threadIdx.x % PT::NTR, m = threadIdx.x / PT::NTR;
+#pragma unroll 1
+  for (int r0 = 0; r0 < H; r0 += PT::MR) {
+    const int y = r0 + m;
+    float2 v[PT::ER];
+    const LdsLine row = plane_row<H, W>(pl, y);
+#pragma unroll
+    for (int e = 0; e < PT::ER; ++e) v[e] = row[t + e * PT::NTR];
+    fft_line<W, true>(v, t, row, twW);
+#pragma unroll
+    for (int e = 0; e < PT::ER; ++e)
+      coef_store(ca + (size_t)y * W + t + e * PT::NTR, Store<DT>::enc_raw(v[e].x * sa));
+    if (ib < R) {
+#pragma unroll
+      for (int e = 0; e < PT::ER; ++e)
+        coef_store(cb + (size_t)y * W + t + e * PT::NTR, Store<DT>::enc_raw(v[e].y * sb));
+    }
+  }
+}
+
+// inverse: coefficients of the pair (decoded, thresholded) -> x DFT -> y DFT
+// -> U slice for the z pass
+template <int H, int W, int DT>
+__global__ void __launch_bounds__((PlaneTile<H, W>::THREADS))
+k_plane_coef_fft(const typename Store<DT>::T *__restrict__ coef, const float *__restrict__ scales,
+                 float2 *__restrict__ U, int D, int R, int b0, int p0, int np, ThrArgs thr,
+                 const float2 *__restrict__ twH, const float2 *__restrict__ twW) {
+  using PT = PlaneTile<H, W>;
+  __shared__ float2 pl[H * PT::RL];
+  const int z = blockIdx.x, pp = blockIdx.y, bl = blockIdx.z, b = b0 + bl;
+  const int ia = 2 * (p0 + pp), ib = ia + 1;
+  const bool has_b = ib < R;
+  const size_t slice = (size_t)H * W, vol = slice * D;
+  float sa = 1.f, sb = 1.f;
+  if (DT != 0) {
+    sa = scales[(size_t)b * R + ia];
+    if (has_b) sb = scales[(size_t)b * R + ib];
+  }
+  float da = 0.f, db = 0.f;
+  if (thr.sigma) {
+    const float sg = thr.sigma[b];
+    const int ja = thr.jof[ia];
+    if (ja >= 0) da = (thr.K[ja] * sg) * thr.l2[ia];
+    if (has_b) {
+      const int jb = thr.jof[ib];
+      if (jb >= 0) db = (thr.K[jb] * sg) * thr.l2[ib];
+    }
+  }
+  using Raw = typename Store<DT>::Raw;
+  const Raw *ca = (const Raw *)(coef + ((size_t)b * R + ia) * vol + (size_t)z * slice);
+  const Raw *cb = (const Raw *)(coef + ((size_t)b * R + (has_b ? ib : ia)) * vol + (size_t)z * slice);
+  const int t = threadIdx.x % PT::NTR, m = threadIdx.x / PT::NTR;
+#pragma unroll 1
+  for (int r0 = 0; r0 < H; r0 += PT::MR) {
+    const int y = r0 + m;
+    Raw ra[PT::ER], rb[PT::ER];
+#pragma unroll
+    for (int e = 0; e < PT::ER; ++e) {
+      ra[e] = coef_load(ca + (size_t)y * W + t + e * PT::NTR);
+      rb[e] = coef_load(cb + (size_t)y * W + t + e * PT::NTR);   // ignored without a partner
+    }
+    float2 v[PT::ER];
+#pragma unroll
+    for (int e = 0; e < PT::ER; ++e) {
+      float a = Store<DT>::dec_raw(ra[e]) * sa;
+      float bb = has_b ? Store<DT>::dec_raw(rb[e]) * sb : 0.f;
+      if (!(fabsf(a) >= da)) a = 0.f;
+      if (!(fabsf(bb) >= db)) bb = 0.f;
+      v[e] = make_float2(a, bb);
+    }
+    const LdsLine row = plane_row<H, W>(pl, y);
+    fft_line<W, false>(v, t, row, twW);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PT::ER; ++e) row[t + e * PT::NTR] = v[e];
+  }
+  __syncthreads();
+  plane_cols<H, W, false>(pl, twH);
+  float2 *Us = U + ((size_t)bl * np + pp) * vol + (size_t)z * slice;
+  for (int k = threadIdx.x; k < H * W; k += PT::THREADS) {
+    const int y = k / W, x = k % W;
+    Us[k] = pl[y * PT::RL + x + (x >> 3)];
+  }
+}
+
+// fused denoise: y IDFT, x IDFT, scale, hard threshold, x DFT, y DFT of one
+// slice, in place
+template <int H, int W>
+__global__ void __launch_bounds__((PlaneTile<H, W>::THREADS))
+k_plane_thr(float2 *__restrict__ T, int D, int R, int b0, int p0, int np, float inv_n,
+            ThrArgs thr, const float2 *__restrict__ twH, const float2 *__restrict__ twW) {
+  using PT = PlaneTile<H, W>;
+  __shared__ float2 pl[H * PT::RL];
+  const int z = blockIdx.x, pp = blockIdx.y, bl = blockIdx.z, b = b0 + bl;
+  const int ia = 2 * (p0 + pp), ib = ia + 1;
+  float da = 0.f, db = 0.f;
+  {
+    const float sg = thr.sigma[b];
+    const int ja = thr.jof[ia];
+    if (ja >= 0) da = (thr.K[ja] * sg) * thr.l2[ia];
+    if (ib < R) {
+      const int jb = thr.jof[ib];
+      if (jb >= 0) db = (thr.K[jb] * sg) * thr.l2[ib];
+    }
+  }
+  const size_t slice = (size_t)H * W, vol = slice * D;
+  float2 *Ts = T + ((size_t)bl * np + pp) * vol + (size_t)z * slice;
+  for (int k = threadIdx.x; k < H * W; k += PT::THREADS) {
+    const int y = k / W, x = k % W;
+    pl[y * PT::RL + x + (x >> 3)] = Ts[k];
+  }
+  __syncthreads();
+  plane_cols<H, W, true>(pl, twH);
+  const int t = threadIdx.x % PT::NTR, m = threadIdx.x / PT::NTR;
+#pragma unroll 1
+  for (int r0 = 0; r0 < H; r0 += PT::MR) {
+    const int y = r0 + m;
+    const LdsLine row = plane_row<H, W>(pl, y);
+    float2 v[PT::ER];
+#pragma unroll
+    for (int e = 0; e < PT::ER; ++e) v[e] = row[t + e * PT::NTR];
+    fft_line<W, true>(v, t, row, twW);
+#pragma unroll
+    for (int e = 0; e < PT::ER; ++e) {
+      float a = v[e].x * inv_n, bb = ib < R ? v[e].y * inv_n : 0.f;
+      if (!(fabsf(a) >= da)) a = 0.f;
+      if (!(fabsf(bb) >= db)) bb = 0.f;
+      v[e] = make_float2(a, bb);
+    }
+    fft_line<W, false>(v, t, row, twW);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PT::ER; ++e) row[t + e * PT::NTR] = v[e];
+  }
+  __syncthreads();
+  plane_cols<H, W, false>(pl, twH);
+  for (int k = threadIdx.x; k < H * W; k += PT::THREADS) {
+    const int y = k / W, x = k % W;
+    Ts[k] = pl[y * PT::RL + x + (x >> 3)];
+  }
+}
+
 #define SL_FOR_EACH_N(X) \
   X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
 
@@ -1003,4 +1226,89 @@ hipError_t launch_rows_real_ifft(const Sys2D &s, const float2 *V, float *x, int 
   return hipGetLastError();
 }
 
+// ---- plane passes of volumes ------------------------------------------------
+// (H, W) slices with an LDS plane kernel; other shapes use the line passes
+#define SL_FOR_EACH_PLANE(X) X(64, 64) X(96, 96) X(128, 128) X(64, 128) X(128, 64) X(96, 128) X(128, 96)
+
+template <int H, int W>
+static constexpr bool plane_ok() { return PlaneTile<H, W>::OK; }
+
+bool plane_supported(int H, int W) {
+#define X(h, w) \
+  if (H == h && W == w) return plane_ok<h, w>();
+  SL_FOR_EACH_PLANE(X)
+#undef X
+  return false;
+}
+
+template <int DT>
+static hipError_t plane_coef_dt(const Sys2D &s, int D, const float2 *T, void *coef,
+                                const float *scales, Chunk c, float inv_n, hipStream_t st) {
+  using CT = typename Store<DT>::T;
+#define X(h, w)                                                                                 \
+  if constexpr (plane_ok<h, w>())                                                               \
+    if (s.H == h && s.W == w) {                                                                 \
+      hipLaunchKernelGGL((k_plane_coef<h, w, DT>), dim3(D, c.np, c.nb),                 \
+                         dim3(PlaneTile<h, w>::THREADS), 0, st, T, (CT *)coef, scales, D, s.R,  \
+                         c.b0, c.p0, c.np, inv_n, s.twH, s.twW);                        \
+      return hipGetLastError();                                                                 \
+    }
+  SL_FOR_EACH_PLANE(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_plane_coef(const Sys2D &s, int D, const float2 *T, void *coef,
+                             const float *scales, Chunk c, float inv_n, hipStream_t st) {
+  switch (s.dtype) {
+    case 0: return plane_coef_dt<0>(s, D, T, coef, scales, c, inv_n, st);
+    case 1: return plane_coef_dt<1>(s, D, T, coef, scales, c, inv_n, st);
+    case 2: return plane_coef_dt<2>(s, D, T, coef, scales, c, inv_n, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int DT>
+static hipError_t plane_coef_fft_dt(const Sys2D &s, int D, const void *coef, const float *scales,
+                                    float2 *U, Chunk c, const ThrArgs &thr, hipStream_t st) {
+  using CT = typename Store<DT>::T;
+#define X(h, w)                                                                                 \
+  if constexpr (plane_ok<h, w>())                                                               \
+    if (s.H == h && s.W == w) {                                                                 \
+      hipLaunchKernelGGL((k_plane_coef_fft<h, w, DT>), dim3(D, c.np, c.nb),             \
+                         dim3(PlaneTile<h, w>::THREADS), 0, st, (const CT *)coef, scales, U, D, \
+                         s.R, c.b0, c.p0, c.np, thr, s.twH, s.twW);                     \
+      return hipGetLastError();                                                                 \
+    }
+  SL_FOR_EACH_PLANE(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_plane_coef_fft(const Sys2D &s, int D, const void *coef, const float *scales,
+                                 float2 *U, Chunk c, const ThrArgs &thr, hipStream_t st) {
+  switch (s.dtype) {
+    case 0: return plane_coef_fft_dt<0>(s, D, coef, scales, U, c, thr, st);
+    case 1: return plane_coef_fft_dt<1>(s, D, coef, scales, U, c, thr, st);
+    case 2: return plane_coef_fft_dt<2>(s, D, coef, scales, U, c, thr, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_plane_thr(const Sys2D &s, int D, float2 *T, float inv_n, Chunk c,
+                            const ThrArgs &thr, hipStream_t st) {
+#define X(h, w)                                                                                 \
+  if constexpr (plane_ok<h, w>())                                                               \
+    if (s.H == h && s.W == w) {                                                                 \
+      hipLaunchKernelGGL((k_plane_thr<h, w>), dim3(D, c.np, c.nb),                      \
+                         dim3(PlaneTile<h, w>::THREADS), 0, st, T, D, s.R, c.b0, c.p0, c.np,    \
+                         inv_n, thr, s.twH, s.twW);                                             \
+      return hipGetLastError();                                                                 \
+    }
+  SL_FOR_EACH_PLANE(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
 }  // namespace sl
+

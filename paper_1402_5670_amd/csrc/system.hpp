@@ -22,6 +22,7 @@ struct sl_system {
   size_t chunk_cap = 0;
   int inv_images = 0;             // images per inverse accumulation block (0 = auto)
   int split_pairs = 1;            // small grids split the pair loop over blocks
+  bool plane3d = true;            // volumes: y and x passes of a z-slice in LDS
   float *d_filt = nullptr;    // 2D: [R][H][W]
   float *d_psi = nullptr;     // Psi_hat on the grid
   float *d_l2 = nullptr, *d_l1 = nullptr;

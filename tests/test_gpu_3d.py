@@ -150,3 +150,41 @@ def test_video_192_three_scales():
     out = s.denoise(xg, sig, [3.0, 3.0, 4.0], coeffs=c)
     torch.cuda.synchronize()
     assert T.psnr(clean, out.cpu().numpy()[0]) > T.psnr(clean, x) + 3.0
+
+
+@pytest.mark.parametrize("dims,J,levels,Bn", [((16, 128, 128), 2, [1, 1], 1),
+                                              ((24, 64, 64), 2, [0, 1], 2),
+                                              ((12, 64, 128), 1, [1], 1),
+                                              ((8, 96, 96), 1, [0], 1)])
+def test_plane_passes_equal_line_passes(monkeypatch, dims, J, levels, Bn):
+    # the z-slice plane kernels run the line passes' FFTs on the same values;
+    # the compiler may contract multiplies and adds differently in the fused
+    # kernels, so results agree to float32 rounding (relative 1e-6), and the
+    # volume still matches the input after forward + inverse; FP16 storage too
+    print(f"case: plane passes {dims} J={J} B={Bn}", flush=True)
+    x = np.random.default_rng(61).standard_normal((Bn, *dims))
+    sig = _gpu(np.full(Bn, 0.5))
+    K = [3.0] * J
+    for dtype in ("f32", "f16"):
+        monkeypatch.setenv("SL_PLANE3D", "0")
+        lines = B.System(dims, J, levels, dtype=dtype)
+        monkeypatch.setenv("SL_PLANE3D", "1")
+        plane = B.System(dims, J, levels, dtype=dtype)
+        xg = _gpu(x)
+        ca, sa = lines.forward(xg)
+        cb, sb = plane.forward(xg)
+        ra = lines.inverse(ca, sa)
+        rb = plane.inverse(cb, sb)
+        ta = lines.inverse(ca, sa, sigma=sig, K=K)
+        tb = plane.inverse(cb, sb, sigma=sig, K=K)
+        torch.cuda.synchronize()
+        pairs = [("forward", ca.float(), cb.float()), ("inverse", ra, rb), ("threshold", ta, tb)]
+        if dtype == "f32":
+            pairs.append(("denoise_fused", lines.denoise_fused(xg, sig, K),
+                          plane.denoise_fused(xg, sig, K)))
+        torch.cuda.synchronize()
+        for name, a, b in pairs:
+            e = rel(b.cpu().numpy(), a.cpu().numpy())
+            print(f"{dtype} {name}: bitwise {torch.equal(a, b)}, relL2 {e:.1e}", flush=True)
+            assert e < (1e-6 if dtype == "f32" else 1e-3), (dtype, name, e)
+        assert rel(rb.cpu().numpy(), x) < (1e-5 if dtype == "f32" else 2e-3)
