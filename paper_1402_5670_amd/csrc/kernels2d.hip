@@ -165,7 +165,7 @@ k_cols_fft(const float2 *__restrict__ A, float2 *__restrict__ F, int W,
   using PL = typename CTile<N>::PL;
   __shared__ float2 lds[M * N];
   const int m = threadIdx.x % M, t = threadIdx.x / M;
-  const int col = blockIdx.x * M + m;
+  const int col = col_tile() * M + m;
   const bool ok = col < W;
   const size_t base = (size_t)blockIdx.y * N * W + (ok ? col : 0);
   float2 v[E];
@@ -196,7 +196,7 @@ k_cols_filter_ifft(const float2 *__restrict__ F, const float *__restrict__ filt,
   using PL = typename CTile<N>::PL;
   __shared__ float2 lds[M * N];
   const int m = threadIdx.x % M, t = threadIdx.x / M;
-  const int col = blockIdx.x * M + m;
+  const int col = col_tile() * M + m;
   const bool ok = col < W;
   const int cc = ok ? col : 0;
   const size_t plane = (size_t)N * W;
@@ -254,7 +254,9 @@ k_cols_filter_ifft(const float2 *__restrict__ F, const float *__restrict__ filt,
 #endif
 // Column tile of the forward filter pass: SL_COLF_M columns per block (at
 // most the generic column tile's width).  8 columns (two blocks per CU) was
-// measured 30% slower than 16 on the 32 x 512^2 batch.
+// measured 30% slower than 16 on the 32 x 512^2 batch with tiles in linear
+// order, 1% slower with the XCD-grouped order of col_tile(); forcing more
+// waves per SIMD (amdgpu_waves_per_eu) spills registers.
 #ifndef SL_COLF_M
 #define SL_COLF_M 16
 #endif
@@ -283,7 +285,7 @@ k_cols_filter_ifft3(const float2 *__restrict__ F, const float *__restrict__ filt
   __shared__ float2 twl[N];
   stage_twiddles<N>(twl, tw);       // the FFT's leading barrier orders it
   const int m = threadIdx.x % M, t = threadIdx.x / M;
-  const int col = blockIdx.x * M + m;
+  const int col = col_tile() * M + m;
   const bool ok = col < W;
   const unsigned o0 = (unsigned)t * W + (ok ? col : 0), se = (unsigned)NT * W;
   const size_t plane = (size_t)N * W;
@@ -349,7 +351,7 @@ k_cols_fft_acc3(const float2 *__restrict__ U, const float *__restrict__ filt,
   __shared__ float2 twl[N];
   stage_twiddles<N>(twl, tw);
   const int m = threadIdx.x % M, t = threadIdx.x / M;
-  const int col = blockIdx.x * M + m;
+  const int col = col_tile() * M + m;
   const bool ok = col < W;
   const unsigned o0 = (unsigned)t * W + (ok ? col : 0), se = (unsigned)NT * W;
   const size_t plane = (size_t)N * W;
@@ -590,7 +592,7 @@ k_cols_fft_acc(const float2 *__restrict__ U, const float *__restrict__ filt,
   using PL = typename CTile<N>::PL;
   __shared__ float2 lds[M * N];
   const int m = threadIdx.x % M, t = threadIdx.x / M;
-  const int col = blockIdx.x * M + m;
+  const int col = col_tile() * M + m;
   const bool ok = col < W;
   const int cc = ok ? col : 0;
   const size_t plane = (size_t)N * W;
@@ -682,7 +684,7 @@ k_cols_acc_finish(float2 *__restrict__ ACC, const float *__restrict__ psi, int W
   using PL = typename CTile<N>::PL;
   __shared__ float2 lds[M * N];
   const int m = threadIdx.x % M, t = threadIdx.x / M;
-  const int col = blockIdx.x * M + m;
+  const int col = col_tile() * M + m;
   const bool ok = col < W;
   const int cc = ok ? col : 0;
   const size_t plane = (size_t)N * W;

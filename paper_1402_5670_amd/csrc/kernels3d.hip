@@ -85,7 +85,7 @@ k_z_filter_ifft(const float2 *__restrict__ F, const Sub3D *__restrict__ subs,
   for (int i = threadIdx.x; i < N; i += blockDim.x) twl[i] = tw[i];
   const int HW = H * W;
   const int m = threadIdx.x % M, t = threadIdx.x / M;
-  const int col = blockIdx.x * M + m;
+  const int col = col_tile() * M + m;
   const bool ok = col < HW;
   const int cc = ok ? col : 0;
   const int y = cc / W, x = cc % W;
@@ -130,7 +130,7 @@ k_z_fft_acc(const float2 *__restrict__ U, const Sub3D *__restrict__ subs,
   for (int i = threadIdx.x; i < N; i += blockDim.x) twl[i] = tw[i];
   const int HW = H * W;
   const int m = threadIdx.x % M, t = threadIdx.x / M;
-  const int col = blockIdx.x * M + m;
+  const int col = col_tile() * M + m;
   const bool ok = col < HW;
   const int cc = ok ? col : 0;
   const int y = cc / W, x = cc % W;
