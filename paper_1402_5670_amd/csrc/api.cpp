@@ -269,7 +269,7 @@ int forward3d(const sl_system *s, const float *x, int batch, void *coef, float *
       if (plane) {
         SL_LAUNCH(P_ROWS_COEF, st, sl::launch_plane_coef(vp, D, T, coef, scales, c, inv_vol, st));
       } else {
-        SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, T, T, c.nb * c.np * D, true, st));
+        SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, T, T, c.nb * c.np * D, true, st, true));
         SL_LAUNCH(P_ROWS_COEF, st, sl::launch_rows_coef(vr, T, coef, scales, c, st));
       }
     }
@@ -294,7 +294,7 @@ int inverse3d(const sl_system *s, const void *coef, const float *scales, int bat
         SL_LAUNCH(P_ROWS_COEF_FFT, st, sl::launch_plane_coef_fft(vp, D, coef, scales, U, c, thr, st));
       } else {
         SL_LAUNCH(P_ROWS_COEF_FFT, st, sl::launch_rows_coef_fft(vr, coef, scales, U, c, thr, st));
-        SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, U, U, c.nb * c.np * D, false, st));
+        SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, U, U, c.nb * c.np * D, false, st, true));
       }
       SL_LAUNCH(P_COLS_FFT_ACC, st,
                 sl::launch_z_fft_acc(v3, U, ACC, c, p0 == 0, p0 + c.np == P, st));
@@ -336,9 +336,9 @@ int denoise_fused_run(const sl_system *s, const float *x_dev, int batch, const s
         if (plane) {
           SL_LAUNCH(P_ROWS_THR, st, sl::launch_plane_thr(vp, D, T, inv_n, c, thr, st));
         } else {
-          SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, T, T, c.nb * c.np * D, true, st));
+          SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, T, T, c.nb * c.np * D, true, st, true));
           SL_LAUNCH(P_ROWS_THR, st, sl::launch_rows_thr(vr, T, inv_n, c, thr, st));
-          SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, T, T, c.nb * c.np * D, false, st));
+          SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, T, T, c.nb * c.np * D, false, st, true));
         }
         SL_LAUNCH(P_COLS_FFT_ACC, st,
                   sl::launch_z_fft_acc(v3, T, ACC, c, p0 == 0, p0 + c.np == P, st));

@@ -42,9 +42,11 @@ bool lines_supported(int n);
 // x [B][H][W] real -> A [B][H][W] complex (row DFT); xmax[b] = max |x_b| bits
 hipError_t launch_rows_real_fft(const Sys2D &s, const float *x, float2 *A, unsigned *xmax, int B,
                                 hipStream_t st);
-// A -> F (column DFT, or inverse DFT without scaling when inverse is set)
+// A -> F (column DFT, or inverse DFT without scaling when inverse is set);
+// stream marks A and F as pair-plane streams read or written once (accessed
+// with the non-temporal hint)
 hipError_t launch_cols_fft(const Sys2D &s, const float2 *A, float2 *F, int B, bool inverse,
-                           hipStream_t st);
+                           hipStream_t st, bool stream = false);
 // F, filters -> T[chunk] (filter pair multiply + column inverse DFT)
 hipError_t launch_cols_filter_ifft(const Sys2D &s, const float2 *F, float2 *T, Chunk c,
                                    hipStream_t st);

@@ -271,4 +271,33 @@ __device__ __forceinline__ int col_tile() {
   return bx;
 }
 
+
+// Pair-plane streams: the complex intermediates that the column passes write
+// once (forward) or read once (inverse), gigabytes per call, while the
+// filter tables read beside them are reused by every image and pair.  With
+// SL_NT_STREAM these accesses carry the non-temporal hint, so the stream
+// does not push the filter lines out of L2.
+#ifndef SL_NT_STREAM
+#define SL_NT_STREAM 1
+#endif
+typedef float sl_f2v __attribute__((ext_vector_type(2)));
+template <bool NT = SL_NT_STREAM>
+__device__ __forceinline__ void stream_store(float2 *p, float2 v) {
+  if constexpr (NT) {
+    const sl_f2v w = {v.x, v.y};
+    __builtin_nontemporal_store(w, (sl_f2v *)p);
+  } else {
+    *p = v;
+  }
+}
+template <bool NT = SL_NT_STREAM>
+__device__ __forceinline__ float2 stream_load(const float2 *p) {
+  if constexpr (NT) {
+    const sl_f2v w = __builtin_nontemporal_load((const sl_f2v *)p);
+    return make_float2(w.x, w.y);
+  } else {
+    return *p;
+  }
+}
+
 }  // namespace sl

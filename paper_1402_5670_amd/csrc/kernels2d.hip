@@ -157,7 +157,8 @@ k_rows_real_fft(const float *__restrict__ x, float2 *__restrict__ A, unsigned *_
   }
 }
 
-template <int N, bool INV>
+// NT: A and F are pair-plane streams (non-temporal accesses)
+template <int N, bool INV, bool NT_>
 __global__ void __launch_bounds__(CTile<N>::THREADS)
 k_cols_fft(const float2 *__restrict__ A, float2 *__restrict__ F, int W,
            const float2 *__restrict__ tw) {
@@ -170,11 +171,11 @@ k_cols_fft(const float2 *__restrict__ A, float2 *__restrict__ F, int W,
   const size_t base = (size_t)blockIdx.y * N * W + (ok ? col : 0);
   float2 v[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = ok ? A[base + (size_t)(t + e * NT) * W] : make_float2(0.f, 0.f);
+  for (int e = 0; e < E; ++e) v[e] = ok ? stream_load<NT_>(&A[base + (size_t)(t + e * NT) * W]) : make_float2(0.f, 0.f);
   fft_line_p<PL, INV>(v, t, LdsLine{lds + m, M}, tw);
   if (ok) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) F[base + (size_t)(t + e * NT) * W] = v[e];
+    for (int e = 0; e < E; ++e) stream_store<NT_>(&F[base + (size_t)(t + e * NT) * W], v[e]);
   }
 }
 
@@ -231,7 +232,7 @@ k_cols_filter_ifft(const float2 *__restrict__ F, const float *__restrict__ filt,
       if (ok && bl < nb) {
         float2 *To = T + ((size_t)bl * np + pp) * plane + col;
 #pragma unroll
-        for (int e = 0; e < E; ++e) To[(size_t)(t + e * NT) * W] = v[e];
+        for (int e = 0; e < E; ++e) stream_store(&To[(size_t)(t + e * NT) * W], v[e]);
       }
     }
   }
@@ -334,7 +335,7 @@ k_cols_filter_ifft3(const float2 *__restrict__ F, const float *__restrict__ filt
       if (ok && bl < nb) {
         float2 *To = T + ((size_t)bl * np + pp) * plane;
 #pragma unroll
-        for (int e = 0; e < E; ++e) To[o0 + e * se] = v[bt][e];
+        for (int e = 0; e < E; ++e) stream_store(&To[o0 + e * se], v[bt][e]);
       }
     }
   }
@@ -385,7 +386,7 @@ k_cols_fft_acc3(const float2 *__restrict__ U, const float *__restrict__ filt,
       const float2 *Ui = U + ((size_t)(bl < nb ? bl : 0) * np + pp) * plane;
       float2 v[E];
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = Ui[o0 + e * se];
+      for (int e = 0; e < E; ++e) v[e] = stream_load(&Ui[o0 + e * se]);
       fft_line_p<PL, false>(v, t, LdsLine{lds + m, M}, TwLds{twl});
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -629,7 +630,7 @@ k_cols_fft_acc(const float2 *__restrict__ U, const float *__restrict__ filt,
       const float2 *Ui = U + ((size_t)(bl < nb ? bl : 0) * np + pp) * plane + cc;
       float2 v[E];
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = Ui[(size_t)(t + e * NT) * W];
+      for (int e = 0; e < E; ++e) v[e] = stream_load(&Ui[(size_t)(t + e * NT) * W]);
       fft_line_p<PL, false>(v, t, LdsLine{lds + m, M}, tw);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -991,16 +992,22 @@ hipError_t launch_rows_real_fft(const Sys2D &s, const float *x, float2 *A, unsig
 }
 
 hipError_t launch_cols_fft(const Sys2D &s, const float2 *A, float2 *F, int B, bool inverse,
-                           hipStream_t st) {
+                           hipStream_t st, bool stream) {
   switch (s.H) {
 #define X(N)                                                                                  \
   case N:                                                                                     \
-    if (inverse)                                                                              \
-      hipLaunchKernelGGL((k_cols_fft<N, true>), col_grid<N>(s.W, B), dim3(CTile<N>::THREADS), 0, \
-                         st, A, F, s.W, s.twH);                                               \
+    if (inverse && stream)                                                                    \
+      hipLaunchKernelGGL((k_cols_fft<N, true, true>), col_grid<N>(s.W, B),                    \
+                         dim3(CTile<N>::THREADS), 0, st, A, F, s.W, s.twH);                   \
+    else if (inverse)                                                                         \
+      hipLaunchKernelGGL((k_cols_fft<N, true, false>), col_grid<N>(s.W, B),                   \
+                         dim3(CTile<N>::THREADS), 0, st, A, F, s.W, s.twH);                   \
+    else if (stream)                                                                          \
+      hipLaunchKernelGGL((k_cols_fft<N, false, true>), col_grid<N>(s.W, B),                   \
+                         dim3(CTile<N>::THREADS), 0, st, A, F, s.W, s.twH);                   \
     else                                                                                      \
-      hipLaunchKernelGGL((k_cols_fft<N, false>), col_grid<N>(s.W, B), dim3(CTile<N>::THREADS), \
-                         0, st, A, F, s.W, s.twH);                                            \
+      hipLaunchKernelGGL((k_cols_fft<N, false, false>), col_grid<N>(s.W, B),                  \
+                         dim3(CTile<N>::THREADS), 0, st, A, F, s.W, s.twH);                   \
     break;
     SL_FOR_EACH_N(X)
 #undef X

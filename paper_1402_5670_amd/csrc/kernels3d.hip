@@ -110,7 +110,7 @@ k_z_filter_ifft(const float2 *__restrict__ F, const Sub3D *__restrict__ subs,
     if (ok) {
       float2 *To = T + ((size_t)blockIdx.y * np + pp) * vol + col;
 #pragma unroll
-      for (int e = 0; e < E; ++e) To[(size_t)(t + e * NT) * HW] = v[e];
+      for (int e = 0; e < E; ++e) stream_store(&To[(size_t)(t + e * NT) * HW], v[e]);
     }
   }
 }
@@ -146,7 +146,7 @@ k_z_fft_acc(const float2 *__restrict__ U, const Sub3D *__restrict__ subs,
     const float2 *Ui = U + ((size_t)blockIdx.y * np + pp) * vol + cc;
     float2 v[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = Ui[(size_t)(t + e * NT) * HW];
+    for (int e = 0; e < E; ++e) v[e] = stream_load(&Ui[(size_t)(t + e * NT) * HW]);
     fft_line_p<Plan<N>, false>(v, t, LdsLine{lds + m, M}, TwLds{twl});
     const ZLine la = zline(subs[ia], tab, y, x);
     const ZLine lb = zline(subs[ib < R ? ib : ia], tab, y, x);
