@@ -451,6 +451,59 @@ k_rows_coef(const float2 *__restrict__ T, typename Store<DT>::T *__restrict__ co
   }
 }
 
+// k_rows_coef with the row-group loop and next-row prefetch of k_rows_thr,
+// used for 16-bit storage, whose stores are half as long (32 x 512^2 FP16:
+// step 2.29 -> 2.21 ms; with FP32 coefficients it was 4% slower)
+template <int N, int DT>
+__global__ void __launch_bounds__(Tile<N>::THREADS / 2 > 0 ? Tile<N>::THREADS / 2 : 1)
+k_rows_coef_pf(const float2 *__restrict__ T, typename Store<DT>::T *__restrict__ coef,
+               const float *__restrict__ scales, int H, int R, int b0, int p0, int np,
+               float inv_hw, const float2 *__restrict__ tw) {
+  constexpr int NT = Tile<N>::NT, E = Tile<N>::E;
+  constexpr int M = Tile<N>::M / 2 > 0 ? Tile<N>::M / 2 : 1;
+  __shared__ float2 lds[M * row_lds_len<N>()];
+  const int t = threadIdx.x % NT, m = threadIdx.x / NT;
+  const int pp = blockIdx.y, bl = blockIdx.z, b = b0 + bl;
+  const int ia = 2 * (p0 + pp), ib = ia + 1;
+  const size_t plane = (size_t)H * N;
+  const float2 *Tp = T + ((size_t)bl * np + pp) * plane;
+  float sa = inv_hw, sb = inv_hw;
+  if (DT != 0) {
+    sa = inv_hw / scales[(size_t)b * R + ia];
+    if (ib < R) sb = inv_hw / scales[(size_t)b * R + ib];
+  }
+  using Raw = typename Store<DT>::Raw;
+  Raw *ca0 = (Raw *)(coef + ((size_t)b * R + ia) * plane);
+  Raw *cb0 = (Raw *)(coef + ((size_t)b * R + (ib < R ? ib : ia)) * plane);
+  const int nrg = (H + M - 1) / M, G = (int)gridDim.x;
+  float2 nx[E];
+  auto load = [&](int rg) {
+    const int row = rg * M + m;
+    const float2 *src = Tp + (size_t)(row < H ? row : 0) * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) nx[e] = src[t + e * NT];
+  };
+  if ((int)blockIdx.x < nrg) load(blockIdx.x);
+  for (int rg = blockIdx.x; rg < nrg; rg += G) {
+    float2 v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = nx[e];
+    if (rg + G < nrg) load(rg + G);
+    fft_line<N, true>(v, t, LdsLine{lds + m * row_lds_len<N>(), 0}, tw);
+    const int row = rg * M + m;
+    if (row < H) {
+      Raw *ca = ca0 + (size_t)row * N;
+#pragma unroll
+      for (int e = 0; e < E; ++e) coef_store(ca + t + e * NT, Store<DT>::enc_raw(v[e].x * sa));
+      if (ib < R) {
+        Raw *cb = cb0 + (size_t)row * N;
+#pragma unroll
+        for (int e = 0; e < E; ++e) coef_store(cb + t + e * NT, Store<DT>::enc_raw(v[e].y * sb));
+      }
+    }
+  }
+}
+
 // scale_{b,i} = 2^(ceil(log2(max|x_b| * ||psi_i||_1)) - 15): |c| <= max|x| ||psi||_1
 // (Young), so the stored values stay below 2^15 in magnitude.
 __global__ void k_scales(const unsigned *__restrict__ xmax, const float *__restrict__ l1,
@@ -535,6 +588,75 @@ k_rows_coef_fft(const typename Store<DT>::T *__restrict__ coef, const float *__r
   }
 }
 
+
+// k_rows_coef_fft with the row-group loop and next-row prefetch (both
+// coefficient rows of the pair) of k_rows_thr, used for 16-bit storage
+// (32 x 512^2 FP16: step 2.24 -> 2.18 ms)
+template <int N, int DT>
+__global__ void __launch_bounds__(Tile<N>::THREADS / 2 > 0 ? Tile<N>::THREADS / 2 : 1)
+k_rows_coef_fft_pf(const typename Store<DT>::T *__restrict__ coef, const float *__restrict__ scales,
+                   float2 *__restrict__ U, int H, int R, int b0, int p0, int np, ThrArgs thr,
+                   const float2 *__restrict__ tw) {
+  constexpr int NT = Tile<N>::NT, E = Tile<N>::E;
+  constexpr int M = Tile<N>::M / 2 > 0 ? Tile<N>::M / 2 : 1;
+  __shared__ float2 lds[M * row_lds_len<N>()];
+  const int t = threadIdx.x % NT, m = threadIdx.x / NT;
+  const int pp = blockIdx.y, bl = blockIdx.z, b = b0 + bl;
+  const int ia = 2 * (p0 + pp), ib = ia + 1;
+  const bool has_b = ib < R;
+  const size_t plane = (size_t)H * N;
+  float sa = 1.f, sb = 1.f;
+  if (DT != 0) {
+    sa = scales[(size_t)b * R + ia];
+    if (has_b) sb = scales[(size_t)b * R + ib];
+  }
+  float da = 0.f, db = 0.f;
+  if (thr.sigma) {
+    const float sg = thr.sigma[b];
+    const int ja = thr.jof[ia];
+    if (ja >= 0) da = (thr.K[ja] * sg) * thr.l2[ia];
+    if (has_b) {
+      const int jb = thr.jof[ib];
+      if (jb >= 0) db = (thr.K[jb] * sg) * thr.l2[ib];
+    }
+  }
+  using Raw = typename Store<DT>::Raw;
+  const Raw *ca0 = (const Raw *)(coef + ((size_t)b * R + ia) * plane);
+  const Raw *cb0 = (const Raw *)(coef + ((size_t)b * R + (has_b ? ib : ia)) * plane);
+  float2 *Up = U + ((size_t)bl * np + pp) * plane;
+  const int nrg = (H + M - 1) / M, G = (int)gridDim.x;
+  Raw na[E], nb_[E];
+  auto load = [&](int rg) {
+    const int row = rg * M + m;
+    const size_t o = (size_t)(row < H ? row : 0) * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      na[e] = coef_load(ca0 + o + t + e * NT);
+      nb_[e] = coef_load(cb0 + o + t + e * NT);   // a valid plane; ignored without a partner
+    }
+  };
+  if ((int)blockIdx.x < nrg) load(blockIdx.x);
+  for (int rg = blockIdx.x; rg < nrg; rg += G) {
+    float2 v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      float a = Store<DT>::dec_raw(na[e]) * sa;
+      float bb = has_b ? Store<DT>::dec_raw(nb_[e]) * sb : 0.f;
+      if (!(fabsf(a) >= da)) a = 0.f;
+      if (!(fabsf(bb) >= db)) bb = 0.f;
+      v[e] = make_float2(a, bb);
+    }
+    if (rg + G < nrg) load(rg + G);
+    fft_line<N, false>(v, t, LdsLine{lds + m * row_lds_len<N>(), 0}, tw);
+    const int row = rg * M + m;
+    if (row < H) {
+      float2 *Uo = Up + (size_t)row * N;
+#pragma unroll
+      for (int e = 0; e < E; ++e) Uo[t + e * NT] = v[e];
+    }
+  }
+}
+
 // Denoising without materialised coefficients: the forward transform's last
 // row pass and the inverse transform's first row pass on one row of a pair
 // plane.  T holds the column-transformed pair (c_a + i c_b before its row
@@ -542,16 +664,27 @@ k_rows_coef_fft(const typename Store<DT>::T *__restrict__ coef, const float *__r
 // k_rows_coef stores them, the hard threshold of k_rows_coef_fft is applied,
 // and the row DFT of the thresholded pair is written back in place (it is
 // the U of the inverse's column pass).
+// The blocks loop over row groups of their plane and load the next group's
+// rows while transforming the current ones (with two FFTs per row the loads
+// are otherwise exposed: 1.07 -> 0.65 ms on 32 x 512^2, R = 49).  Blocks are
+// half the height of the other row passes' (the loop keeps its twiddles in
+// registers).  The loop is uniform over the block, so the FFT's
+// synchronisation is too; rows past H are computed on row 0's values and not
+// stored.
 template <int N>
-__global__ void __launch_bounds__(Tile<N>::THREADS)
-k_rows_thr(float2 *__restrict__ T, int H, int R, int b0, int p0, int np, float inv_n, ThrArgs thr,
-           const float2 *__restrict__ tw) {
-  constexpr int NT = Tile<N>::NT, M = Tile<N>::M, E = Tile<N>::E;
+struct PTile {
+  static constexpr int NT = Tile<N>::NT, E = Tile<N>::E;
+  static constexpr int M = Tile<N>::M / 2 > 0 ? Tile<N>::M / 2 : 1;
+  static constexpr int THREADS = M * NT;
+};
+
+template <int N>
+__global__ void __launch_bounds__(PTile<N>::THREADS)
+k_rows_thr(float2 *__restrict__ T, int H, int R, int b0, int p0, int np, float inv_n,
+           ThrArgs thr, const float2 *__restrict__ tw) {
+  constexpr int NT = PTile<N>::NT, M = PTile<N>::M, E = PTile<N>::E;
   __shared__ float2 lds[M * row_lds_len<N>()];
   const int t = threadIdx.x % NT, m = threadIdx.x / NT;
-  const int row = blockIdx.x * M + m;
-  const bool ok = row < H;
-  const int rr = ok ? row : 0;
   const int pp = blockIdx.y, bl = blockIdx.z, b = b0 + bl;
   const int ia = 2 * (p0 + pp), ib = ia + 1;
   float da = 0.f, db = 0.f;
@@ -564,33 +697,61 @@ k_rows_thr(float2 *__restrict__ T, int H, int R, int b0, int p0, int np, float i
       if (jb >= 0) db = (thr.K[jb] * sg) * thr.l2[ib];
     }
   }
-  float2 *Ti = T + ((size_t)bl * np + pp) * (size_t)H * N + (size_t)rr * N;
-  float2 v[E];
+  float2 *Tp = T + ((size_t)bl * np + pp) * (size_t)H * N;
+  const int nrg = (H + M - 1) / M, G = (int)gridDim.x;
+  float2 nx[E];
+  auto load = [&](int rg) {
+    const int row = rg * M + m;
+    const float2 *src = Tp + (size_t)(row < H ? row : 0) * N;
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = Ti[t + e * NT];
-  fft_line<N, true>(v, t, LdsLine{lds + m * row_lds_len<N>(), 0}, tw);
+    for (int e = 0; e < E; ++e) nx[e] = src[t + e * NT];
+  };
+  if ((int)blockIdx.x < nrg) load(blockIdx.x);
+  for (int rg = blockIdx.x; rg < nrg; rg += G) {
+    float2 v[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    float a = v[e].x * inv_n, bb = ib < R ? v[e].y * inv_n : 0.f;
-    if (!(fabsf(a) >= da)) a = 0.f;
-    if (!(fabsf(bb) >= db)) bb = 0.f;
-    v[e] = make_float2(a, bb);
-  }
-  fft_line<N, false>(v, t, LdsLine{lds + m * row_lds_len<N>(), 0}, tw);
-  if (ok) {
+    for (int e = 0; e < E; ++e) v[e] = nx[e];
+    if (rg + G < nrg) load(rg + G);
+    fft_line<N, true>(v, t, LdsLine{lds + m * row_lds_len<N>(), 0}, tw);
 #pragma unroll
-    for (int e = 0; e < E; ++e) Ti[t + e * NT] = v[e];
+    for (int e = 0; e < E; ++e) {
+      float a = v[e].x * inv_n, bb = ib < R ? v[e].y * inv_n : 0.f;
+      if (!(fabsf(a) >= da)) a = 0.f;
+      if (!(fabsf(bb) >= db)) bb = 0.f;
+      v[e] = make_float2(a, bb);
+    }
+    fft_line<N, false>(v, t, LdsLine{lds + m * row_lds_len<N>(), 0}, tw);
+    const int row = rg * M + m;
+    if (row < H) {
+      float2 *dst = Tp + (size_t)row * N;
+#pragma unroll
+      for (int e = 0; e < E; ++e) dst[t + e * NT] = v[e];
+    }
   }
 }
 
+// Column tile of the inverse accumulation pass: SL_COLI_M columns per block
+// (at most the generic column tile's width).
+#ifndef SL_COLI_M
+#define SL_COLI_M 16
+#endif
+template <int N>
+struct ITile {
+  using PL = Plan<N>;
+  static constexpr int NT = PL::NT;
+  static constexpr int E = PL::E;
+  static constexpr int M = CTile<N>::M < SL_COLI_M ? CTile<N>::M : SL_COLI_M;
+  static constexpr int THREADS = M * NT;
+};
+
 template <int N, int BT>
-__global__ void __launch_bounds__(CTile<N>::THREADS)
+__global__ void __launch_bounds__(ITile<N>::THREADS)
 k_cols_fft_acc(const float2 *__restrict__ U, const float *__restrict__ filt,
                const float *__restrict__ psi, float2 *__restrict__ ACC, float2 *__restrict__ part,
                int Btot, int W, int R, int b0, int nb, int p0, int np, int first, int last,
                const float2 *__restrict__ tw) {
-  constexpr int NT = CTile<N>::NT, M = CTile<N>::M, E = CTile<N>::E;
-  using PL = typename CTile<N>::PL;
+  constexpr int NT = ITile<N>::NT, M = ITile<N>::M, E = ITile<N>::E;
+  using PL = typename ITile<N>::PL;
   __shared__ float2 lds[M * N];
   const int m = threadIdx.x % M, t = threadIdx.x / M;
   const int col = col_tile() * M + m;
@@ -1045,7 +1206,7 @@ int inv_pair_groups(const Sys2D &s, int nb, int np) {
   switch (s.H) {
 #define X(N) \
   case N:    \
-    M = CTile<N>::M; \
+    M = ITile<N>::M; \
     break;
     SL_FOR_EACH_N(X)
 #undef X
@@ -1087,9 +1248,18 @@ static hipError_t rows_coef_dt(const Sys2D &s, const float2 *T, void *coef, cons
   switch (s.W) {
 #define X(N)                                                                                     \
   case N:                                                                                        \
-    hipLaunchKernelGGL((k_rows_coef<N, DT>), row_grid<N>(s.H, c.np, c.nb),                       \
-                       dim3(Tile<N>::THREADS), 0, st, T, (CT *)coef, scales, s.H, s.R, c.b0, c.p0, \
-                       c.np, inv_hw, s.twW);                                                     \
+    if (DT != 0) {                                                                               \
+      constexpr int MP = Tile<N>::M / 2 > 0 ? Tile<N>::M / 2 : 1;                                \
+      const int nrg = (s.H + MP - 1) / MP;                                                       \
+      int G = nrg / 8 > 1 ? nrg / 8 : 1;                                                         \
+      if ((long)G * c.np * c.nb < 8L * s.num_cu) G = nrg;                                        \
+      hipLaunchKernelGGL((k_rows_coef_pf<N, DT>), dim3(G, c.np, c.nb), dim3(MP * Tile<N>::NT), 0, \
+                         st, T, (CT *)coef, scales, s.H, s.R, c.b0, c.p0, c.np, inv_hw, s.twW);  \
+    } else {                                                                                     \
+      hipLaunchKernelGGL((k_rows_coef<N, DT>), row_grid<N>(s.H, c.np, c.nb),                     \
+                         dim3(Tile<N>::THREADS), 0, st, T, (CT *)coef, scales, s.H, s.R, c.b0,   \
+                         c.p0, c.np, inv_hw, s.twW);                                             \
+    }                                                                                            \
     break;
     SL_FOR_EACH_N(X)
 #undef X
@@ -1131,9 +1301,19 @@ static hipError_t rows_coef_fft_dt(const Sys2D &s, const void *coef, const float
   switch (s.W) {
 #define X(N)                                                                                   \
   case N:                                                                                      \
-    hipLaunchKernelGGL((k_rows_coef_fft<N, DT>), row_grid<N>(s.H, c.np, c.nb),                 \
-                       dim3(Tile<N>::THREADS), 0, st, (const CT *)coef, scales, U, s.H, s.R,   \
-                       c.b0, c.p0, c.np, thr, s.twW);                                          \
+    if (DT != 0) {                                                                             \
+      constexpr int MP = Tile<N>::M / 2 > 0 ? Tile<N>::M / 2 : 1;                              \
+      const int nrg = (s.H + MP - 1) / MP;                                                     \
+      int G = nrg / 8 > 1 ? nrg / 8 : 1;                                                       \
+      if ((long)G * c.np * c.nb < 8L * s.num_cu) G = nrg;                                      \
+      hipLaunchKernelGGL((k_rows_coef_fft_pf<N, DT>), dim3(G, c.np, c.nb),                     \
+                         dim3(MP * Tile<N>::NT), 0, st, (const CT *)coef, scales, U, s.H, s.R, \
+                         c.b0, c.p0, c.np, thr, s.twW);                                        \
+    } else {                                                                                   \
+      hipLaunchKernelGGL((k_rows_coef_fft<N, DT>), row_grid<N>(s.H, c.np, c.nb),               \
+                         dim3(Tile<N>::THREADS), 0, st, (const CT *)coef, scales, U, s.H, s.R, \
+                         c.b0, c.p0, c.np, thr, s.twW);                                        \
+    }                                                                                          \
     break;
     SL_FOR_EACH_N(X)
 #undef X
@@ -1154,10 +1334,15 @@ hipError_t launch_rows_thr(const Sys2D &s, float2 *T, float inv_n, Chunk c, cons
                            hipStream_t st) {
   switch (s.W) {
 #define X(N)                                                                                   \
-  case N:                                                                                      \
-    hipLaunchKernelGGL(k_rows_thr<N>, row_grid<N>(s.H, c.np, c.nb), dim3(Tile<N>::THREADS), 0, \
-                       st, T, s.H, s.R, c.b0, c.p0, c.np, inv_n, thr, s.twW);                  \
-    break;
+  case N: {                                                                                    \
+    /* about 8 row groups per block, unless that leaves the GPU short of blocks */             \
+    const int nrg = (s.H + PTile<N>::M - 1) / PTile<N>::M;                                     \
+    int G = nrg / 8 > 1 ? nrg / 8 : 1;                                                         \
+    if ((long)G * c.np * c.nb < 8L * s.num_cu) G = nrg;                                        \
+    hipLaunchKernelGGL(k_rows_thr<N>, dim3(G, c.np, c.nb), dim3(PTile<N>::THREADS), 0, st, T,  \
+                       s.H, s.R, c.b0, c.p0, c.np, inv_n, thr, s.twW);                         \
+    break;                                                                                     \
+  }
     SL_FOR_EACH_N(X)
 #undef X
     default:
@@ -1178,14 +1363,14 @@ hipError_t launch_cols_fft_acc(const Sys2D &s, const float2 *U, float2 *ACC, flo
                          c.nb, c.p0, c.np, (int)first, (int)last, s.twH);                      \
     else if (inv_bt(s, c.nb) == 1)                                                              \
       hipLaunchKernelGGL((k_cols_fft_acc<N, 1>),                                                \
-                         dim3((s.W + CTile<N>::M - 1) / CTile<N>::M, c.nb, G),                  \
-                         dim3(CTile<N>::THREADS), 0, st, U, s.filt, s.psi, ACC, part, Btot,     \
+                         dim3((s.W + ITile<N>::M - 1) / ITile<N>::M, c.nb, G),                  \
+                         dim3(ITile<N>::THREADS), 0, st, U, s.filt, s.psi, ACC, part, Btot,     \
                          s.W, s.R, c.b0, c.nb, c.p0, c.np, (int)first, (int)(last && G == 1),   \
                          s.twH);                                                                \
     else                                                                                        \
       hipLaunchKernelGGL((k_cols_fft_acc<N, kInvBT>),                                           \
-                         dim3((s.W + CTile<N>::M - 1) / CTile<N>::M, (c.nb + kInvBT - 1) / kInvBT, G), \
-                         dim3(CTile<N>::THREADS), 0, st, U, s.filt, s.psi, ACC, part, Btot,     \
+                         dim3((s.W + ITile<N>::M - 1) / ITile<N>::M, (c.nb + kInvBT - 1) / kInvBT, G), \
+                         dim3(ITile<N>::THREADS), 0, st, U, s.filt, s.psi, ACC, part, Btot,     \
                          s.W, s.R, c.b0, c.nb, c.p0, c.np, (int)first, (int)(last && G == 1),   \
                          s.twH);                                                                \
     break;
