@@ -230,6 +230,39 @@ def test_denoise_fused_matches(monkeypatch, dims, J, levels, Bn, chunk_mb):
                                          None))
 
 
+@pytest.mark.parametrize("dims,J,levels,Bn", [
+    ((192, 64), 3, [1, 1, 2], 64),      # 24 row groups of 8, 3 blocks per plane
+    ((12, 64), 2, [1, 1], 240),         # 2 row groups per block, the last one ragged
+])
+def test_row_group_loop_large_batch(dims, J, levels, Bn):
+    # enough pair planes that the fused threshold row pass and the 16-bit
+    # coefficient row passes give each block several row groups (of 8 rows
+    # for 64-sample rows) of its plane: the loop with next-row prefetch
+    print(f"case: row-group loop {dims} J={J} B={Bn}", flush=True)
+    H = dims[0]
+    sig = np.array([0.05 + 0.0005 * b for b in range(Bn)], dtype=np.float32)
+    xs = np.stack([syn.noisy_cartoon2d(*dims, 700 + b, float(sig[b]))[1] for b in range(Bn)])
+    K = np.array([3.0] * (J - 1) + [4.0], dtype=np.float32)
+    xg, sg = _gpu(xs), _gpu(sig)
+    s32 = B.System(dims, J, levels)
+    nrg = (H + 7) // 8
+    G = max(1, nrg // 8)
+    assert G * ((s32.R + 1) // 2) * Bn >= 8 * 256 and nrg > G   # the loop runs (256 CUs)
+    ref = s32.denoise(xg, sg, K)
+    got = s32.denoise_fused(xg, sg, K)
+    torch.cuda.synchronize()
+    assert rel(got.cpu().numpy(), ref.cpu().numpy()) < 1e-6
+    o = S.build_2d(dims, J, levels)
+    s16 = B.System(dims, J, levels, dtype="f16")
+    c, sc = s16.forward(xg)
+    xr = s16.inverse(c, sc)
+    torch.cuda.synchronize()
+    cd = _decode(c, sc)
+    for b in (0, Bn // 2 + 1, Bn - 1):
+        assert rel(cd[b], T.forward(xs[b], o.filters)) < 2e-3, b
+    assert rel(xr.cpu().numpy(), xs) < 2e-3
+
+
 def test_chunked_schedule_matches(monkeypatch):
     print("case: chunk size 1 MiB vs default", flush=True)
     x = np.random.default_rng(9).standard_normal((3, 64, 64))
