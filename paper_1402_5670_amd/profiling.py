@@ -35,6 +35,7 @@ def source_hash():
 
 
 def short_name(k):
+    k = k.replace("(anonymous namespace)::", "")
     return k.split("(")[0].replace("void ", "").strip()
 
 
