@@ -730,28 +730,29 @@ k_rows_thr(float2 *__restrict__ T, int H, int R, int b0, int p0, int np, float i
   }
 }
 
-// Column tile of the inverse accumulation pass: SL_COLI_M columns per block
-// (at most the generic column tile's width).
-#ifndef SL_COLI_M
-#define SL_COLI_M 16
-#endif
-template <int N>
+// Column tile of the inverse accumulation pass: MW columns per block (at
+// most the generic column tile's width).  16 columns for batches; a single
+// image takes 8 (512 threads, no register spills, twice the blocks): one
+// 512^2 image, R = 49, 5% faster per inpainting iteration, while the
+// 32-image batch is 34% slower with 8.
+constexpr int kInvWide = 16, kInvNarrow = 8;
+template <int N, int MW>
 struct ITile {
   using PL = Plan<N>;
   static constexpr int NT = PL::NT;
   static constexpr int E = PL::E;
-  static constexpr int M = CTile<N>::M < SL_COLI_M ? CTile<N>::M : SL_COLI_M;
+  static constexpr int M = CTile<N>::M < MW ? CTile<N>::M : MW;
   static constexpr int THREADS = M * NT;
 };
 
-template <int N, int BT>
-__global__ void __launch_bounds__(ITile<N>::THREADS)
+template <int N, int BT, int MW>
+__global__ void __launch_bounds__((ITile<N, MW>::THREADS))
 k_cols_fft_acc(const float2 *__restrict__ U, const float *__restrict__ filt,
                const float *__restrict__ psi, float2 *__restrict__ ACC, float2 *__restrict__ part,
                int Btot, int W, int R, int b0, int nb, int p0, int np, int first, int last,
                const float2 *__restrict__ tw) {
-  constexpr int NT = ITile<N>::NT, M = ITile<N>::M, E = ITile<N>::E;
-  using PL = typename ITile<N>::PL;
+  constexpr int NT = ITile<N, MW>::NT, M = ITile<N, MW>::M, E = ITile<N, MW>::E;
+  using PL = typename ITile<N, MW>::PL;
   __shared__ float2 lds[M * N];
   const int m = threadIdx.x % M, t = threadIdx.x / M;
   const int col = col_tile() * M + m;
@@ -1206,7 +1207,7 @@ int inv_pair_groups(const Sys2D &s, int nb, int np) {
   switch (s.H) {
 #define X(N) \
   case N:    \
-    M = ITile<N>::M; \
+    M = nb == 1 ? ITile<N, kInvNarrow>::M : ITile<N, kInvWide>::M; \
     break;
     SL_FOR_EACH_N(X)
 #undef X
@@ -1361,18 +1362,25 @@ hipError_t launch_cols_fft_acc(const Sys2D &s, const float2 *U, float2 *ACC, flo
       hipLaunchKernelGGL((k_cols_fft_acc3<N, kInvBT>), col_grid<N>(s.W, (c.nb + kInvBT - 1) / kInvBT), \
                          dim3(CTile<N>::THREADS), 0, st, U, s.filt, s.psi, ACC, s.W, s.R, c.b0, \
                          c.nb, c.p0, c.np, (int)first, (int)last, s.twH);                      \
+    else if (c.nb == 1)                                                                         \
+      hipLaunchKernelGGL((k_cols_fft_acc<N, 1, kInvNarrow>),                                    \
+                         dim3((s.W + ITile<N, kInvNarrow>::M - 1) / ITile<N, kInvNarrow>::M, 1, G), \
+                         dim3(ITile<N, kInvNarrow>::THREADS), 0, st, U, s.filt, s.psi, ACC, part, \
+                         Btot, s.W, s.R, c.b0, c.nb, c.p0, c.np, (int)first,                    \
+                         (int)(last && G == 1), s.twH);                                         \
     else if (inv_bt(s, c.nb) == 1)                                                              \
-      hipLaunchKernelGGL((k_cols_fft_acc<N, 1>),                                                \
-                         dim3((s.W + ITile<N>::M - 1) / ITile<N>::M, c.nb, G),                  \
-                         dim3(ITile<N>::THREADS), 0, st, U, s.filt, s.psi, ACC, part, Btot,     \
-                         s.W, s.R, c.b0, c.nb, c.p0, c.np, (int)first, (int)(last && G == 1),   \
-                         s.twH);                                                                \
+      hipLaunchKernelGGL((k_cols_fft_acc<N, 1, kInvWide>),                                      \
+                         dim3((s.W + ITile<N, kInvWide>::M - 1) / ITile<N, kInvWide>::M, c.nb, G), \
+                         dim3(ITile<N, kInvWide>::THREADS), 0, st, U, s.filt, s.psi, ACC, part, \
+                         Btot, s.W, s.R, c.b0, c.nb, c.p0, c.np, (int)first,                    \
+                         (int)(last && G == 1), s.twH);                                         \
     else                                                                                        \
-      hipLaunchKernelGGL((k_cols_fft_acc<N, kInvBT>),                                           \
-                         dim3((s.W + ITile<N>::M - 1) / ITile<N>::M, (c.nb + kInvBT - 1) / kInvBT, G), \
-                         dim3(ITile<N>::THREADS), 0, st, U, s.filt, s.psi, ACC, part, Btot,     \
-                         s.W, s.R, c.b0, c.nb, c.p0, c.np, (int)first, (int)(last && G == 1),   \
-                         s.twH);                                                                \
+      hipLaunchKernelGGL((k_cols_fft_acc<N, kInvBT, kInvWide>),                                 \
+                         dim3((s.W + ITile<N, kInvWide>::M - 1) / ITile<N, kInvWide>::M,        \
+                              (c.nb + kInvBT - 1) / kInvBT, G),                                 \
+                         dim3(ITile<N, kInvWide>::THREADS), 0, st, U, s.filt, s.psi, ACC, part, \
+                         Btot, s.W, s.R, c.b0, c.nb, c.p0, c.np, (int)first,                    \
+                         (int)(last && G == 1), s.twH);                                         \
     break;
     SL_FOR_EACH_N(X)
 #undef X
