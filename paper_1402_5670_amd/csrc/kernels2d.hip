@@ -253,20 +253,20 @@ k_cols_filter_ifft(const float2 *__restrict__ F, const float *__restrict__ filt,
 #ifndef SL_COL_V3_INV
 #define SL_COL_V3_INV 0
 #endif
-// Column tile of the forward filter pass: SL_COLF_M columns per block (at
-// most the generic column tile's width).  8 columns (two blocks per CU) was
-// measured 30% slower than 16 on the 32 x 512^2 batch with tiles in linear
-// order, 1% slower with the XCD-grouped order of col_tile(); forcing more
-// waves per SIMD (amdgpu_waves_per_eu) spills registers.
-#ifndef SL_COLF_M
-#define SL_COLF_M 16
-#endif
-template <int N>
+// Column tile of the forward filter pass: MW columns per block (at most the
+// generic column tile's width).  On the 32 x 512^2 batch 8 columns (two
+// blocks per CU) was 30% slower than 16 with tiles in linear order; with the
+// XCD-grouped order of col_tile() the step is the same and the fused denoise
+// 1.5% slower, while a single image gains (one 512^2 image, R = 49: 4% per
+// inpainting iteration), so a chunk of one image takes 8 columns.  Forcing
+// more waves per SIMD (amdgpu_waves_per_eu) spills registers.
+constexpr int kFwdWide = 16, kFwdNarrow = 8;
+template <int N, int MW>
 struct FTile {
   using PL = Plan<N>;
   static constexpr int NT = PL::NT;
   static constexpr int E = PL::E;
-  static constexpr int M = CTile<N>::M < SL_COLF_M ? CTile<N>::M : SL_COLF_M;
+  static constexpr int M = CTile<N>::M < MW ? CTile<N>::M : MW;
   static constexpr int THREADS = M * NT;
 };
 
@@ -275,13 +275,13 @@ __device__ __forceinline__ void stage_twiddles(float2 *twl, const float2 *__rest
   for (int i = threadIdx.x; i < N; i += blockDim.x) twl[i] = tw[i];
 }
 
-template <int N, int BT>
-__global__ void __launch_bounds__(FTile<N>::THREADS)
+template <int N, int BT, int MW>
+__global__ void __launch_bounds__((FTile<N, MW>::THREADS))
 k_cols_filter_ifft3(const float2 *__restrict__ F, const float *__restrict__ filt,
                     float2 *__restrict__ T, int W, int R, int b0, int nb, int p0, int np,
                     const float2 *__restrict__ tw) {
-  constexpr int NT = FTile<N>::NT, M = FTile<N>::M, E = FTile<N>::E;
-  using PL = typename FTile<N>::PL;
+  constexpr int NT = FTile<N, MW>::NT, M = FTile<N, MW>::M, E = FTile<N, MW>::E;
+  using PL = typename FTile<N, MW>::PL;
   __shared__ float2 lds[M * N];
   __shared__ float2 twl[N];
   stage_twiddles<N>(twl, tw);       // the FFT's leading barrier orders it
@@ -1216,18 +1216,24 @@ int inv_pair_groups(const Sys2D &s, int nb, int np) {
   return pair_groups(s, ((s.W + M - 1) / M) * ((nb + bt - 1) / bt), np, 2, 16);
 }
 
+template <int N, int MW>
+static void launch_fwd3(const Sys2D &s, const float2 *F, float2 *T, Chunk c, hipStream_t st) {
+  using FT = FTile<N, MW>;
+  const int tiles = (s.W + FT::M - 1) / FT::M, ny = (c.nb + kFwdBT - 1) / kFwdBT;
+  hipLaunchKernelGGL((k_cols_filter_ifft3<N, kFwdBT, MW>),
+                     dim3(tiles, ny, pair_groups(s, tiles * ny, c.np, 4, 32)), dim3(FT::THREADS),
+                     0, st, F, s.filt, T, s.W, s.R, c.b0, c.nb, c.p0, c.np, s.twH);
+}
+
 hipError_t launch_cols_filter_ifft(const Sys2D &s, const float2 *F, float2 *T, Chunk c,
                                    hipStream_t st) {
   switch (s.H) {
 #define X(N)                                                                                 \
   case N:                                                                                    \
-    if (SL_COL_V3_FWD)                                                                         \
-      hipLaunchKernelGGL((k_cols_filter_ifft3<N, kFwdBT>),                                      \
-                         dim3((s.W + FTile<N>::M - 1) / FTile<N>::M, (c.nb + kFwdBT - 1) / kFwdBT, \
-                              pair_groups(s, ((s.W + FTile<N>::M - 1) / FTile<N>::M) *         \
-                                                 ((c.nb + kFwdBT - 1) / kFwdBT), c.np, 4, 32)),   \
-                         dim3(FTile<N>::THREADS), 0, st, F, s.filt, T, s.W, s.R, c.b0, c.nb, c.p0, \
-                         c.np, s.twH);                                                         \
+    if (SL_COL_V3_FWD && c.nb == 1)                                                            \
+      launch_fwd3<N, kFwdNarrow>(s, F, T, c, st);                                              \
+    else if (SL_COL_V3_FWD)                                                                    \
+      launch_fwd3<N, kFwdWide>(s, F, T, c, st);                                                \
     else                                                                                       \
       hipLaunchKernelGGL((k_cols_filter_ifft<N, kFwdBT>), col_grid<N>(s.W, (c.nb + kFwdBT - 1) / kFwdBT), \
                          dim3(CTile<N>::THREADS), 0, st, F, s.filt, T, s.W, s.R, c.b0, c.nb, c.p0, \
