@@ -309,7 +309,7 @@ int inverse3d(const sl_system *s, const void *coef, const float *scales, int bat
 // materialising the coefficients (the body of sl_denoise_fused and of every
 // inpainting iteration).  Arguments are validated by the callers.
 int denoise_fused_run(const sl_system *s, const float *x_dev, int batch, const sl::ThrArgs &thr,
-                      float *out_dev, char *ws, hipStream_t st) {
+                      float *out_dev, char *ws, hipStream_t st, const sl::MixArgs *mix = nullptr) {
   const Layout L = layout(s, batch);
   float2 *F = (float2 *)(ws + L.off_F);
   float2 *ACC = (float2 *)(ws + L.off_acc);
@@ -326,7 +326,10 @@ int denoise_fused_run(const sl_system *s, const float *x_dev, int batch, const s
     const sl::Sys2D vp = view2d(s, H, W, H, W);
     const bool plane = s->plane3d && sl::plane_supported(H, W);
     const sl::Sys3D v3 = view3d(s);
-    SL_LAUNCH(P_ROWS_REAL_FFT, st, sl::launch_rows_real_fft(vr, x_dev, F, nullptr, batch, st));
+    if (mix)
+      SL_LAUNCH(P_ROWS_REAL_FFT, st, sl::launch_rows_real_fft_mix(vr, *mix, F, batch, st));
+    else
+      SL_LAUNCH(P_ROWS_REAL_FFT, st, sl::launch_rows_real_fft(vr, x_dev, F, nullptr, batch, st));
     SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, F, F, batch * D, false, st));
     SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vz, F, F, batch, false, st));
     for (int b0 = 0; b0 < batch; b0 += nb)
@@ -350,7 +353,10 @@ int denoise_fused_run(const sl_system *s, const float *x_dev, int batch, const s
   const sl::Sys2D v = view2d(s);
   const int G = inv_groups(s, batch);
   float2 *part = (float2 *)(ws + L.off_part);
-  SL_LAUNCH(P_ROWS_REAL_FFT, st, sl::launch_rows_real_fft(v, x_dev, F, nullptr, batch, st));
+  if (mix)
+    SL_LAUNCH(P_ROWS_REAL_FFT, st, sl::launch_rows_real_fft_mix(v, *mix, F, batch, st));
+  else
+    SL_LAUNCH(P_ROWS_REAL_FFT, st, sl::launch_rows_real_fft(v, x_dev, F, nullptr, batch, st));
   SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(v, F, F, batch, false, st));
   for (int b0 = 0; b0 < batch; b0 += nb)
     for (int p0 = 0; p0 < P; p0 += np) {
@@ -365,17 +371,17 @@ int denoise_fused_run(const sl_system *s, const float *x_dev, int batch, const s
   return SL_OK;
 }
 
-// Inpainting workspace: the transform's, then g [B][npix] float32 (the
-// iteration's input) and sigma [B] float32 (the iteration's threshold scale).
+// Inpainting workspace: the transform's, then sigma [B] float32 (the
+// iteration's threshold scale).  The iteration's input is formed while the
+// forward row pass loads it and is not stored.
 struct InpaintLayout {
-  size_t base, off_g, off_sigma, total;
+  size_t base, off_sigma, total;
 };
 
 InpaintLayout inpaint_layout(const sl_system *s, int B) {
   InpaintLayout L;
   L.base = layout(s, B).total;
-  L.off_g = L.base;
-  L.off_sigma = align_up(L.off_g + 4ull * (size_t)s->cfg.npix() * B);
+  L.off_sigma = L.base;
   L.total = align_up(L.off_sigma + 4ull * B);
   return L;
 }
@@ -400,20 +406,17 @@ float schedule_factor(double delta_min, int iterations, int t) {
 
 int inpaint_launches(const sl_system *s, const InpaintArgs &a, hipStream_t st) {
   const InpaintLayout L = inpaint_layout(s, a.batch);
-  float *g = (float *)(a.ws + L.off_g);
   float *sigma = (float *)(a.ws + L.off_sigma);
   sl::ThrArgs thr{};
   thr.sigma = sigma;
   thr.l2 = s->d_l2;
   thr.jof = s->d_jof;
   for (int j = 0; j < s->cfg.J; ++j) thr.K[j] = 1.0f;
-  const size_t n = (size_t)s->cfg.npix() * a.batch;
   for (int t = a.t_begin; t < a.t_end; ++t) {
-    SL_LAUNCH(P_AUX, st,
-              sl::launch_inpaint_mix(a.fm, a.mask, a.f, g, n, t == 0, a.delta_init,
-                                     schedule_factor(a.delta_min, a.iterations, t), sigma,
-                                     a.batch, st));
-    int rc = denoise_fused_run(s, g, a.batch, thr, a.f, a.ws, st);
+    // g = M f_masked + (1 - M) f, formed by the forward row pass
+    const sl::MixArgs mix{a.fm, a.mask, a.f, t == 0 ? 1 : 0, a.delta_init,
+                          schedule_factor(a.delta_min, a.iterations, t), sigma};
+    int rc = denoise_fused_run(s, nullptr, a.batch, thr, a.f, a.ws, st, &mix);
     if (rc) return rc;
   }
   return SL_OK;

@@ -42,6 +42,22 @@ bool lines_supported(int n);
 // x [B][H][W] real -> A [B][H][W] complex (row DFT); xmax[b] = max |x_b| bits
 hipError_t launch_rows_real_fft(const Sys2D &s, const float *x, float2 *A, unsigned *xmax, int B,
                                 hipStream_t st);
+// Inpainting input of one iteration (Algorithm 3), formed while the rows are
+// loaded: x = fm where mask != 0, else f (0 when first: the iteration starts
+// from f = 0 and f is not read).  The launch also writes the iteration's
+// threshold scale sigma[b] = delta_init[b] * fac, b < B.
+struct MixArgs {
+  const float *fm;
+  const uint8_t *mask;
+  const float *f;
+  int first;
+  const float *delta_init;
+  float fac;
+  float *sigma;
+};
+// launch_rows_real_fft with x formed by MixArgs (no max-|x|)
+hipError_t launch_rows_real_fft_mix(const Sys2D &s, const MixArgs &mix, float2 *A, int B,
+                                    hipStream_t st);
 // A -> F (column DFT, or inverse DFT without scaling when inverse is set);
 // stream marks A and F as pair-plane streams read or written once (accessed
 // with the non-temporal hint)

@@ -112,21 +112,36 @@ __device__ __forceinline__ float wave_max(float v) {
 // ---------------------------------------------------------------------------
 // forward
 // ---------------------------------------------------------------------------
-template <int N>
+// MIX = 0: rows of x; MIX = 1 / 2: rows of the inpainting input (MixArgs),
+// first iteration / later ones.
+template <int N, int MIX>
 __global__ void __launch_bounds__(Tile<N>::THREADS)
 k_rows_real_fft(const float *__restrict__ x, float2 *__restrict__ A, unsigned *__restrict__ xmax,
-                int H, const float2 *__restrict__ tw) {
+                int H, const float2 *__restrict__ tw, MixArgs mix, int B) {
   constexpr int NT = Tile<N>::NT, M = Tile<N>::M, E = Tile<N>::E;
   __shared__ float2 lds[M * row_lds_len<N>()];
   const int t = threadIdx.x % NT, m = threadIdx.x / NT;
   const int row = blockIdx.x * M + m, b = blockIdx.y;
   const bool ok = row < H;
   const size_t off = ((size_t)b * H + (ok ? row : 0)) * N;
+  if (MIX && blockIdx.x == 0 && blockIdx.y == 0)
+    for (int i = threadIdx.x; i < B; i += blockDim.x) mix.sigma[i] = mix.delta_init[i] * mix.fac;
   float2 v[E];
   float amax = 0.f;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    float a = ok ? x[off + t + e * NT] : 0.f;
+    float a = 0.f;
+    if (ok) {
+      const size_t i = off + t + e * NT;
+      if constexpr (MIX == 0) {
+        a = x[i];
+      } else {
+        // all three loads issued together, then the selection
+        const unsigned char known = mix.mask[i];
+        const float fm = mix.fm[i], fe = MIX == 2 ? mix.f[i] : 0.f;
+        a = known ? fm : fe;
+      }
+    }
     v[e] = make_float2(a, 0.f);
     amax = fmaxf(amax, fabsf(a));
   }
@@ -1137,13 +1152,33 @@ static dim3 col_grid(int W, int y) {
   return dim3((W + CTile<N>::M - 1) / CTile<N>::M, y, 1);
 }
 
+hipError_t launch_rows_real_fft_mix(const Sys2D &s, const MixArgs &mix, float2 *A, int B,
+                                    hipStream_t st) {
+  switch (s.W) {
+#define X(N)                                                                                  \
+  case N:                                                                                     \
+    if (mix.first)                                                                            \
+      hipLaunchKernelGGL((k_rows_real_fft<N, 1>), row_grid<N>(s.H, B), dim3(Tile<N>::THREADS), \
+                         0, st, nullptr, A, nullptr, s.H, s.twW, mix, B);                     \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_rows_real_fft<N, 2>), row_grid<N>(s.H, B), dim3(Tile<N>::THREADS), \
+                         0, st, nullptr, A, nullptr, s.H, s.twW, mix, B);                     \
+    break;
+    SL_FOR_EACH_N(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_rows_real_fft(const Sys2D &s, const float *x, float2 *A, unsigned *xmax, int B,
                                 hipStream_t st) {
   switch (s.W) {
 #define X(N)                                                                                  \
   case N:                                                                                     \
-    hipLaunchKernelGGL(k_rows_real_fft<N>, row_grid<N>(s.H, B), dim3(Tile<N>::THREADS), 0, st, \
-                       x, A, xmax, s.H, s.twW);                                               \
+    hipLaunchKernelGGL((k_rows_real_fft<N, 0>), row_grid<N>(s.H, B), dim3(Tile<N>::THREADS), 0, \
+                       st, x, A, xmax, s.H, s.twW, MixArgs{}, 0);                             \
     break;
     SL_FOR_EACH_N(X)
 #undef X
