@@ -254,7 +254,6 @@ __device__ __forceinline__ void fft_line(float2 (&v)[Plan<N>::E], int t, const L
   fft_line_p<Plan<N>, INV, wave_lines<Plan<N>::NT>()>(v, t, lds, tw);
 }
 
-
 // Column tile of a column-pass block.  Workgroups go to the eight XCDs of
 // the chip round robin by linear workgroup id; when the x extent of the grid
 // is a multiple of 8, blockIdx.x % 8 is the XCD, and the remap hands each XCD
@@ -271,12 +270,13 @@ __device__ __forceinline__ int col_tile() {
   return bx;
 }
 
-
 // Pair-plane streams: the complex intermediates that the column passes write
-// once (forward) or read once (inverse), gigabytes per call, while the
-// filter tables read beside them are reused by every image and pair.  With
-// SL_NT_STREAM these accesses carry the non-temporal hint, so the stream
-// does not push the filter lines out of L2.
+// once (forward) or read once (inverse), gigabytes per call, beside filter
+// tables that every image and pair re-reads.  With SL_NT_STREAM these
+// accesses carry the non-temporal hint.  Measured on MI355X, 32 x 512^2,
+// R = 49: forward column pass 770 -> 442 us, inverse accumulation
+// 586 -> 540 us, with the same HBM bytes in the counters (the gain is in how
+// the caches treat the stream, not in fewer bytes).
 #ifndef SL_NT_STREAM
 #define SL_NT_STREAM 1
 #endif
