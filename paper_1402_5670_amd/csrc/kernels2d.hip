@@ -273,8 +273,11 @@ k_cols_filter_ifft(const float2 *__restrict__ F, const float *__restrict__ filt,
 // blocks per CU) was 30% slower than 16 with tiles in linear order; with the
 // XCD-grouped order of col_tile() the step is the same and the fused denoise
 // 1.5% slower, while a single image gains (one 512^2 image, R = 49: 4% per
-// inpainting iteration), so a chunk of one image takes 8 columns.  Forcing
-// more waves per SIMD (amdgpu_waves_per_eu) spills registers.
+// inpainting iteration), so a chunk of one image takes 8 columns; its pair
+// planes (50 MB at 512^2, R = 49) stay in the Infinity Cache between the
+// passes, so that instance stores them without the non-temporal hint (3% per
+// iteration).  Forcing more waves per SIMD (amdgpu_waves_per_eu) spills
+// registers.
 constexpr int kFwdWide = 16, kFwdNarrow = 8;
 template <int N, int MW>
 struct FTile {
@@ -350,7 +353,7 @@ k_cols_filter_ifft3(const float2 *__restrict__ F, const float *__restrict__ filt
       if (ok && bl < nb) {
         float2 *To = T + ((size_t)bl * np + pp) * plane;
 #pragma unroll
-        for (int e = 0; e < E; ++e) stream_store(&To[o0 + e * se], v[bt][e]);
+        for (int e = 0; e < E; ++e) stream_store<SL_NT_STREAM && MW != kFwdNarrow>(&To[o0 + e * se], v[bt][e]);
       }
     }
   }
@@ -752,7 +755,9 @@ k_rows_thr(float2 *__restrict__ T, int H, int R, int b0, int p0, int np, float i
 // most the generic column tile's width).  16 columns for batches; a single
 // image takes 8 (512 threads, no register spills, twice the blocks): one
 // 512^2 image, R = 49, 5% faster per inpainting iteration, while the
-// 32-image batch is 34% slower with 8.
+// 32-image batch is 34% slower with 8.  The one-image instance reads the
+// pair planes without the non-temporal hint (they stay in the Infinity
+// Cache).
 constexpr int kInvWide = 16, kInvNarrow = 8;
 template <int N, int MW>
 struct ITile {
@@ -810,7 +815,7 @@ k_cols_fft_acc(const float2 *__restrict__ U, const float *__restrict__ filt,
       const float2 *Ui = U + ((size_t)(bl < nb ? bl : 0) * np + pp) * plane + cc;
       float2 v[E];
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = stream_load(&Ui[(size_t)(t + e * NT) * W]);
+      for (int e = 0; e < E; ++e) v[e] = stream_load<SL_NT_STREAM && MW != kInvNarrow>(&Ui[(size_t)(t + e * NT) * W]);
       fft_line_p<PL, false>(v, t, LdsLine{lds + m, M}, tw);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
