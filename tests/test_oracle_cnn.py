@@ -95,3 +95,36 @@ def test_gain_range_and_shape():
     c = np.random.default_rng(6).standard_normal((9, 11))
     g, _ = cnn.forward(p, c, 0.1, 0.5, bf16=True)
     assert g.shape == c.shape and np.all(g > 0) and np.all(g < 1)
+
+
+def test_adam_three_steps_hand_values():
+    # Kingma and Ba's update with beta1 = 9/10, beta2 = 999/1000, lr = 1/10 and
+    # gradients 1/2, -1/4, 1/8.  The moments, worked out by hand in exact
+    # fractions, are
+    #   m1 = 1/20,   v1 = 1/4000
+    #   m2 = 9/10 * 1/20 - 1/10 * 1/4   = 1/50
+    #   v2 = 999/1000 * 1/4000 + 1/1000 * 1/16 = 1249/4000000
+    #   m3 = 9/10 * 1/50 + 1/10 * 1/8   = 61/2000
+    #   v3 = 999/1000 * 1249/4000000 + 1/1000 * 1/64 = 1310251/4000000000
+    # and the bias-corrected step t is lr * (m_t / (1 - beta1^t)) /
+    # (sqrt(v_t / (1 - beta2^t)) + eps).  From t = 2 on the two betas enter
+    # differently, so swapping them, using g instead of g^2 in v, or dropping
+    # the bias correction each changes these values.
+    p = {"w": np.array([1.0])}
+    st = {}
+    grads = [0.5, -0.25, 0.125]
+    m_hand = [1 / 20, 1 / 50, 61 / 2000]
+    v_hand = [1 / 4000, 1249 / 4000000, 1310251 / 4000000000]
+    w = 1.0
+    for t, g in enumerate(grads, start=1):
+        cnn.adam_step(p, {"w": np.array([g])}, st, lr=0.1)
+        assert abs(st["m_w"][0] - m_hand[t - 1]) < 1e-14 * m_hand[t - 1]
+        assert abs(st["v_w"][0] - v_hand[t - 1]) < 1e-14 * v_hand[t - 1]
+        mh = m_hand[t - 1] / (1 - 0.9 ** t)
+        vh = v_hand[t - 1] / (1 - 0.999 ** t)
+        w -= 0.1 * mh / (np.sqrt(vh) + 1e-8)
+        assert abs(p["w"][0] - w) < 1e-14, (t, p["w"][0], w)
+    # the values after steps 2 and 3 (bias corrections 2/19, 1249/7996 at t = 2)
+    assert abs((1.0 - 0.1 * 0.5 / (0.5 + 1e-8)) - 0.1 * (2 / 19) / (np.sqrt(1249 / 7996) + 1e-8)
+               - 0.8733662987078462) < 1e-14
+    assert abs(p["w"][0] - 0.839323384916654) < 1e-13
