@@ -86,19 +86,36 @@ def measured_traffic(pass_name):
     return None
 
 
-def cpu_baseline(seconds, sigmas, K, H, W, J, levels):
-    """FP64 oracle (numpy FFT, one thread) on a bounded sample of images."""
-    import numpy as np
-    from oracle import system as S
+def host_cpu():
+    """CPU model name and logical core count of this host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
+
+
+def _oracle_image(n, sigmas, K, sysm, H, W):
     from oracle import transform as T
     from paper_1402_5670_amd import synthetic as syn
+    sg = float(sigmas[n % len(sigmas)])
+    _, x = syn.noisy_cartoon2d(H, W, 2000 + n, sg)
+    T.denoise(x, sysm, sg, K)
+
+
+def cpu_baseline(seconds, sigmas, K, H, W, J, levels):
+    """FP64 oracle (numpy FFT, one thread) on a bounded sample of images."""
+    from oracle import system as S
     sysm = S.build_2d((H, W), J, levels)
     n = 0
     t0 = time.perf_counter()
     while True:
-        clean, x = syn.noisy_cartoon2d(H, W, 2000 + n, float(sigmas[n % len(sigmas)]))
-        ts = time.perf_counter()
-        T.denoise(x, sysm, float(sigmas[n % len(sigmas)]), K)
+        _oracle_image(n, sigmas, K, sysm, H, W)
         n += 1
         if time.perf_counter() - t0 >= seconds or n >= 64:
             break
@@ -107,6 +124,48 @@ def cpu_baseline(seconds, sigmas, K, H, W, J, levels):
     return dict(value=coeffs / el, unit="coefficients/s", cores=1, kind="oracle",
                 sample=f"{n} images {H}x{W}, R={sysm.R}, fwd + hard threshold + inv in FP64 "
                        f"(numpy.fft, single thread), filter build excluded, {el:.1f} s")
+
+
+def _oracle_worker(rank, nproc, seconds, sigmas, K, H, W, J, levels, barrier, queue):
+    # one process of the all-cores baseline: build the system, wait for the
+    # others, then run the unmodified oracle on images rank, rank + nproc, ...
+    os.environ["OMP_NUM_THREADS"] = "1"
+    from oracle import system as S
+    sysm = S.build_2d((H, W), J, levels)
+    barrier.wait()
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < seconds:
+        _oracle_image(rank + n * nproc, sigmas, K, sysm, H, W)
+        n += 1
+    queue.put((n, t0, time.perf_counter(), sysm.R))
+
+
+def cpu_baseline_all_cores(seconds, sigmas, K, H, W, J, levels, max_procs=16):
+    """The same FP64 oracle run by one process per core (at most max_procs, the
+    host share of one GPU), each on its own images; the oracle itself is left
+    as it is (numpy.fft), so the parallelism is over images."""
+    import multiprocessing as mp
+    model, ncpu = host_cpu()
+    nproc = max(1, min(ncpu, max_procs))
+    ctx = mp.get_context("spawn")
+    barrier = ctx.Barrier(nproc)
+    queue = ctx.Queue()
+    procs = [ctx.Process(target=_oracle_worker,
+                         args=(r, nproc, seconds, list(map(float, sigmas)), list(K), H, W, J,
+                               list(levels), barrier, queue)) for r in range(nproc)]
+    for p in procs:
+        p.start()
+    res = [queue.get(timeout=600) for _ in procs]
+    for p in procs:
+        p.join()
+    n = sum(r[0] for r in res)
+    el = max(r[2] for r in res) - min(r[1] for r in res)
+    R = res[0][3]
+    return dict(value=n * R * H * W / el, unit="coefficients/s", cores=nproc, kind="oracle",
+                sample=f"{n} images {H}x{W}, R={R}, fwd + hard threshold + inv in FP64 "
+                       f"(numpy.fft), {nproc} processes of one thread each on their own "
+                       f"images, filter build excluded, {el:.1f} s")
 
 
 def psnr(ref, est):
@@ -458,7 +517,11 @@ def main():
     if not args.no_inpaint:
         res["inpainting"] = inpainting_runs()
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(args.cpu_seconds, sig, K, H, W, J, levels)
+        cb = cpu_baseline(args.cpu_seconds, sig, K, H, W, J, levels)
+        allc = cpu_baseline_all_cores(args.cpu_seconds, sig, K, H, W, J, levels)
+        model, ncpu = host_cpu()
+        cb.update({"host_cpu": model, "host_nproc": ncpu, "all_cores": allc})
+        res["cpu_baseline"] = cb
     print(json.dumps(res))
 
 

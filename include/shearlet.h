@@ -123,6 +123,16 @@ void sl_free_system(sl_system *s);
 int sl_system_num_subbands(const sl_system *s, int *R_out);
 int sl_system_subband(const sl_system *s, int i, sl_subband *out);
 
+/* The filter bank of a built system in FP64, as evaluated before it was
+ * rounded to float32 for the device (the same closed form as
+ * sl_build_filters_host / sl_build_wavelet_filters_host on the system's
+ * configuration): filters_host [R][dims] psi_hat_i on the DFT grid (R times
+ * the sample count doubles, caller-owned); dual_host [dims] the dual-frame
+ * weight Psi_hat = sum_i psi_hat_i^2 of eq. frame_filter.  Host memory only;
+ * no GPU work.  SL_EINVAL for NULL arguments.                               */
+int sl_get_filters(const sl_system *s, double *filters_host);
+int sl_get_dual_weight(const sl_system *s, double *dual_host);
+
 /* Device bytes of workspace needed by forward/inverse/denoise for a batch.
  * Every workspace pointer must be 16-byte aligned (SL_EINVAL otherwise).   */
 int sl_workspace_size(const sl_system *s, int batch, size_t *bytes_out);
@@ -149,11 +159,35 @@ int sl_inverse(const sl_system *s, const void *coeffs_dev, const float *scales_d
                int batch, const float *sigma_dev, const float *K_host, float *x_dev,
                void *workspace_dev, size_t workspace_bytes, void *stream);
 
-/* Hard-threshold denoising T^-1 T_delta T x (Section 5.3): sl_forward into
- * coeffs_dev (caller-provided, [B][R][dims]) then sl_inverse with sigma.     */
+/* A trained learned-shrinkage network (see the learned-shrinkage calls
+ * below): its float32 master parameters [J][SL_CNN_PARAMS] and the bfloat16
+ * operand pack sl_cnn_pack built from them.  Both device buffers stay owned
+ * by the caller.                                                            */
+typedef struct {
+  const float *params_dev;
+  const void *packed_dev;
+} sl_shrinkage_model;
+
+/* Denoising T^-1 S T x: sl_forward into coeffs_dev (caller-provided,
+ * [B][R][dims]), the shrinkage S, then the inverse (Section 5.3).
+ *   model == NULL: S is the hard threshold of eq. hard_tresholding inside
+ *     sl_inverse (kept iff |c| >= K[j] sigma[b] ||psi_i||_2, lowpass kept);
+ *     sigma_dev and K_host are required and the workspace is
+ *     sl_workspace_size(s, B) bytes.
+ *   model != NULL: S multiplies every detail coefficient by the network's
+ *     gain (sl_cnn_apply, the lowpass kept) and sl_inverse reconstructs
+ *     without a threshold, so the result equals sl_forward, sl_cnn_apply and
+ *     sl_inverse called in turn; K_host is ignored (may be NULL), the system
+ *     must be a 2D SL_F32 one, and the workspace is
+ *     sl_denoise_workspace_size(s, B, 1, ...) bytes (it holds the shrunk
+ *     coefficients besides the transform's workspace).
+ * Errors: SL_EINVAL for NULL or misaligned buffers or an unsupported system,
+ * SL_ENOMEM for a short workspace.                                          */
+int sl_denoise_workspace_size(const sl_system *s, int batch, int with_model, size_t *bytes_out);
 int sl_denoise(const sl_system *s, const float *x_dev, int batch, const float *sigma_dev,
-               const float *K_host, void *coeffs_dev, float *scales_dev, float *out_dev,
-               void *workspace_dev, size_t workspace_bytes, void *stream);
+               const float *K_host, const sl_shrinkage_model *model, void *coeffs_dev,
+               float *scales_dev, float *out_dev, void *workspace_dev, size_t workspace_bytes,
+               void *stream);
 
 /* Hard-threshold denoising without materialising the coefficients: the
  * forward transform's last row DFT, the threshold of eq. hard_tresholding
@@ -252,7 +286,10 @@ int sl_system_set_block_shape(sl_system *s, int inv_images, int split_pairs);
 int sl_system_block_shape(const sl_system *s, int *inv_images, int *split_pairs);
 
 /* ---- uneven batches (several image sizes in one schedule) ----------------
- * A multi-batch groups n_classes size classes: class s has its own system
+ * The forward (and inverse) transform of a batch of images of different
+ * sizes: sl_multi_run with what = 1 is the uneven-batch forward call
+ * (Algorithm 1 applied to every image with the system of its size), what = 2
+ * the inverse (Algorithm 2), 3 both.  A multi-batch groups n_classes size classes: class s has its own system
  * (not owned; must outlive the multi-batch) and counts[s] images stored
  * contiguously ([counts[s]][dims_s]).  The buffer arguments below are arrays
  * of n_classes device pointers, one per class.  what: 1 = forward,

@@ -13,15 +13,16 @@ lowpass h_J (x) h_J, then for j = 0..J-1 (coarse to fine)
 built spatially (upsampled convolution cascades, tensor products,
 periodisation, DFT) like the shearlet filters.
 
-Algorithm 4, from f0 = f1 = 0 with the schedule of Algorithm 3:
-    f_res = f - (f0 + f1)
-    f0 = T0^-1 T_delta T0 (f_res + f0)      (shearlets)
-    f1 = T1^-1 T_delta T1 (f_res + f1)      (wavelets)
-    delta = lambda * delta
-Both updates use the f_res of the iteration's start.  Readings: T_delta
-thresholds subband i of either system at delta ||psi_i||_2 and keeps its
-lowpass (as in inpainting); the optional total-variation correction the
-paper mentions is not applied.
+Algorithm 4 splits f into two parts, each sparse in one of two transforms
+(here the shearlets for curve-like content and the wavelets for point-like
+content).  Both parts start at zero.  In every pass each part is re-estimated
+by hard-threshold denoising, in its own transform, of what the other part
+leaves of f, i.e. f minus the other part's estimate from the start of the
+pass; both parts are updated from the same starting estimates.  The
+threshold follows the geometric schedule of Algorithm 3.  Readings: either
+system thresholds subband i at delta ||psi_i||_2 and keeps its lowpass (as
+in inpainting); the optional total-variation correction the paper mentions
+is not applied.
 """
 import numpy as np
 
@@ -59,9 +60,9 @@ def build_wavelet_2d(dims, n_scales, qmf=None):
 
 def decompose(f, sys0, sys1, delta_init, delta_min, iterations, start=None, t_begin=0,
               t_end=None):
-    """Algorithm 4.  Returns (f0, f1).  With t_begin / t_end only iterations
-    t_begin..t_end-1 of the schedule run, from start = (f0, f1) after
-    t_begin iterations (zeros when t_begin = 0)."""
+    """Algorithm 4: returns the two parts (f0, f1).  With t_begin / t_end only
+    passes t_begin..t_end-1 of the schedule run, from start = (f0, f1) after
+    t_begin passes (zeros when t_begin = 0)."""
     f = np.asarray(f, dtype=np.float64)
     deltas = I.schedule(delta_init, delta_min, iterations)
     t_end = iterations if t_end is None else t_end
@@ -70,9 +71,7 @@ def decompose(f, sys0, sys1, delta_init, delta_min, iterations, start=None, t_be
     else:
         f0, f1 = (np.asarray(a, dtype=np.float64).copy() for a in start)
     for t in range(t_begin, t_end):
-        f_res = f - (f0 + f1)
-        c0 = I.threshold_all(T.forward(f_res + f0, sys0.filters), sys0, deltas[t])
-        c1 = I.threshold_all(T.forward(f_res + f1, sys1.filters), sys1, deltas[t])
-        f0 = T.inverse(c0, sys0.filters, sys0.dual_weight)
-        f1 = T.inverse(c1, sys1.filters, sys1.dual_weight)
+        # both parts from the estimates at the start of the pass
+        f0, f1 = (I.denoise_at(f - f1, sys0, deltas[t]),
+                  I.denoise_at(f - f0, sys1, deltas[t]))
     return f0, f1

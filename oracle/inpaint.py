@@ -1,26 +1,28 @@
-"""Inpainting by iterative hard thresholding (Section 5, "Image Inpainting",
-Algorithm 3; "Video Inpainting" runs the same scheme on volumes).  FP64.
+"""Inpainting by iterative hard thresholding (Section 5, image inpainting,
+Algorithm 3; video inpainting applies the same scheme to volumes).  FP64.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Given the occluded signal f_masked = M .* f and the binary mask M (1 where the
-signal is known), Algorithm 3 starts from f_inp = 0 and a threshold
-delta = delta_init, and repeats `iterations` times:
-
-    f_res = M .* (f_masked - f_inp)
-    f_inp = T^-1 T_delta T (f_res + f_inp)
-    delta = lambda * delta,    lambda = delta_min ** (1 / (iterations - 1))
-
-so the last iteration thresholds at delta_init * delta_min.
+The method is a fixed-point iteration with a shrinking threshold.  The
+estimate starts at zero.  Each pass first merges the observation with the
+estimate: samples the mask marks as known take their observed value, the
+others keep the current estimate.  The merged signal is then denoised by
+hard thresholding in the shearlet domain (forward transform, threshold,
+dual-frame inverse), and the result becomes the new estimate.  The threshold
+starts at delta_init and is multiplied by the same ratio after every pass,
+the ratio being chosen so that the last pass thresholds at
+delta_init * delta_min.
 
 Readings of points the paper leaves open:
-  * T_delta is the hard-thresholding operator of eq. hard_tresholding applied
-    as in the denoising experiment: subband i is thresholded at
-    delta * ||psi_i||_2 (the coefficient's own scale) and the lowpass is
-    kept.  The schedule therefore runs over normalised thresholds.
-  * delta_min is a ratio (the printed lambda does not involve delta_init),
-    so the last threshold is delta_init * delta_min; one iteration uses
-    delta_init alone.
+  * the threshold operator is the one of eq. hard_tresholding used as in the
+    denoising experiment: subband i is thresholded at delta * ||psi_i||_2
+    (the coefficient's own scale) and the lowpass is kept, so the schedule
+    runs over normalised thresholds;
+  * delta_min is a ratio (the printed decay factor does not involve
+    delta_init), so the last threshold is delta_init * delta_min; a single
+    pass uses delta_init alone;
+  * the mask is binary (1 = known); the merge M f_masked + (1 - M) f is then
+    an exact selection.
 """
 import numpy as np
 
@@ -45,19 +47,29 @@ def threshold_all(c, system, delta):
     return np.stack([T.hard_threshold(ci, di) for ci, di in zip(c, d)])
 
 
-def step(f_inp, f_masked, mask, system, delta):
-    """One pass of the loop body of Algorithm 3."""
+def merge_known(f_est, f_masked, mask):
+    """Observed values on the known samples, the estimate elsewhere:
+    M f_masked + (1 - M) f_est (an exact selection for a binary mask)."""
     m = np.asarray(mask, dtype=np.float64)
-    f_res = m * (np.asarray(f_masked, dtype=np.float64) - f_inp)
-    c = T.forward(f_res + f_inp, system.filters)
-    return T.inverse(threshold_all(c, system, delta), system.filters, system.dual_weight)
+    return m * np.asarray(f_masked, dtype=np.float64) + (1.0 - m) * f_est
+
+
+def denoise_at(g, system, delta):
+    """Hard-threshold denoising of g at the normalised threshold delta."""
+    c = threshold_all(T.forward(g, system.filters), system, delta)
+    return T.inverse(c, system.filters, system.dual_weight)
+
+
+def step(f_est, f_masked, mask, system, delta):
+    """One pass of Algorithm 3: merge, then denoise at delta."""
+    return denoise_at(merge_known(f_est, f_masked, mask), system, delta)
 
 
 def inpaint(f_masked, mask, system, delta_init, delta_min, iterations, f_start=None, t_begin=0,
             t_end=None):
-    """Algorithm 3.  With t_begin / t_end only iterations t_begin..t_end-1 of
-    the `iterations`-step schedule run, starting from f_start (the state
-    after t_begin iterations; zero when t_begin = 0)."""
+    """Algorithm 3: `iterations` passes from a zero estimate.  With t_begin /
+    t_end only passes t_begin..t_end-1 of the schedule run, starting from
+    f_start (the estimate after t_begin passes; zero when t_begin = 0)."""
     deltas = schedule(delta_init, delta_min, iterations)
     t_end = iterations if t_end is None else t_end
     f = np.zeros(np.shape(f_masked)) if t_begin == 0 or f_start is None else \

@@ -42,6 +42,10 @@ class Config(ctypes.Structure):
     ]
 
 
+class ShrinkageModel(ctypes.Structure):
+    _fields_ = [("params_dev", ctypes.c_void_p), ("packed_dev", ctypes.c_void_p)]
+
+
 class Subband(ctypes.Structure):
     _fields_ = [("cone", ctypes.c_int), ("j", ctypes.c_int), ("k1", ctypes.c_int),
                 ("k2", ctypes.c_int), ("l2norm", ctypes.c_double), ("l1norm", ctypes.c_double)]
@@ -69,7 +73,12 @@ _SIGS = {
                     ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
     "sl_denoise": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                    ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
+                   ctypes.c_int),
+    "sl_denoise_workspace_size": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "sl_get_filters": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "sl_get_dual_weight": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "sl_denoise_fused": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                           ctypes.c_void_p], ctypes.c_int),
@@ -352,7 +361,28 @@ class System:
                                        _stream()))
         return coeffs
 
-    def denoise(self, x, sigma, K, coeffs=None, scales=None, out=None, workspace=None):
+    def get_filters(self):
+        """FP64 filter bank [R, *dims] of the built system (host)."""
+        f = np.empty((self.R, *self.dims), dtype=np.float64)
+        check(lib().sl_get_filters(self._h, f.ctypes.data))
+        return f
+
+    def get_dual_weight(self):
+        """FP64 dual-frame weight Psi_hat [*dims] of the built system (host)."""
+        d = np.empty(self.dims, dtype=np.float64)
+        check(lib().sl_get_dual_weight(self._h, d.ctypes.data))
+        return d
+
+    def denoise_workspace_bytes(self, batch, with_model):
+        n = ctypes.c_size_t()
+        check(lib().sl_denoise_workspace_size(self._h, int(batch), int(bool(with_model)),
+                                              ctypes.byref(n)))
+        return n.value
+
+    def denoise(self, x, sigma, K=None, coeffs=None, scales=None, out=None, workspace=None,
+                model=None):
+        """T^-1 S T x with S the hard threshold (model None) or the learned
+        shrinkage of a Shrinkage network."""
         import torch
         self._check_x(x)
         B = x.shape[0]
@@ -360,13 +390,23 @@ class System:
             coeffs, scales = self.alloc_coeffs(B, x.device)
         if out is None:
             out = torch.empty_like(x)
-        ws = workspace if workspace is not None else self.workspace(B, x.device)
-        Kh = (ctypes.c_float * len(K))(*[float(k) for k in K])
-        check(lib().sl_denoise(self._h, _ptr(x), B, _ptr(sigma), ctypes.cast(Kh, ctypes.c_void_p),
-                               _ptr(coeffs), _ptr(scales), _ptr(out), _ptr(ws), ws.numel(),
+        if model is None:
+            ws = workspace if workspace is not None else self.workspace(B, x.device)
+            Kh = (ctypes.c_float * len(K))(*[float(k) for k in K])
+            mp = None
+        else:
+            if workspace is None:
+                workspace = torch.empty(self.denoise_workspace_bytes(B, True), dtype=torch.uint8,
+                                        device=x.device)
+            ws = workspace
+            Kh = None
+            m = ShrinkageModel(_ptr(model.params), _ptr(model.packed))
+            mp = ctypes.byref(m)
+        check(lib().sl_denoise(self._h, _ptr(x), B, _ptr(sigma),
+                               ctypes.cast(Kh, ctypes.c_void_p) if Kh is not None else None,
+                               mp, _ptr(coeffs), _ptr(scales), _ptr(out), _ptr(ws), ws.numel(),
                                _stream()))
         return out
-
 
     def denoise_fused(self, x, sigma, K, out=None, workspace=None):
         """Hard-threshold denoising without materialised coefficients (float32)."""

@@ -226,7 +226,7 @@ struct Timing {
   }
 } g_timing;
 
-// set while sl_inpaint captures a graph: no timing events go into it
+// set while a call captures a graph: no timing events go into it
 thread_local bool g_capturing = false;
 
 template <class F>
@@ -504,6 +504,11 @@ uint64_t bits_of(double v) {
 }  // namespace
 
 int sl::set_error(int code, const std::string &msg) { return fail(code, msg); }
+bool sl::set_capturing(bool on) {
+  const bool was = g_capturing;
+  g_capturing = on;
+  return was;
+}
 int sl::hip_error(hipError_t e, const char *what) { return hip_fail(e, what); }
 
 size_t sl::transform_workspace_bytes(const sl_system *s, int batch) {
@@ -512,7 +517,7 @@ size_t sl::transform_workspace_bytes(const sl_system *s, int batch) {
 
 extern "C" {
 
-int sl_abi_version(void) { return 1; }
+int sl_abi_version(void) { return 2; }
 
 const char *sl_last_error(void) { return g_err.c_str(); }
 
@@ -593,6 +598,7 @@ int build_system_impl(const sl_config *cfg, bool wavelet, sl_system **out) {
   }
   s->subs = bank.subbands;
   s->R = R;
+  s->wavelet = wavelet;
   s->l2 = bank.l2;
   s->l1 = bank.l1;
   if (hipGetDevice(&s->device) != hipSuccess) {
@@ -854,17 +860,90 @@ int sl_denoise_fused(const sl_system *s, const float *x_dev, int batch, const fl
                            (hipStream_t)stream);
 }
 
-int sl_denoise(const sl_system *s, const float *x_dev, int batch, const float *sigma_dev,
-               const float *K_host, void *coeffs_dev, float *scales_dev, float *out_dev,
-               void *workspace_dev, size_t workspace_bytes, void *stream) {
-  if (!sigma_dev || !K_host) return fail(SL_EINVAL, "sigma_dev and K_host are required");
-  int rc = sl_forward(s, x_dev, batch, coeffs_dev, scales_dev, workspace_dev, workspace_bytes,
-                      stream);
-  if (rc) return rc;
-  return sl_inverse(s, coeffs_dev, scales_dev, batch, sigma_dev, K_host, out_dev, workspace_dev,
-                    workspace_bytes, stream);
+namespace {
+size_t al256(size_t v) { return (v + 255) / 256 * 256; }
+}  // namespace
+
+int sl_denoise_workspace_size(const sl_system *s, int batch, int with_model, size_t *bytes_out) {
+  if (!s || !bytes_out) return fail(SL_EINVAL, "NULL argument");
+  if (batch < 1) return fail(SL_EINVAL, "batch must be >= 1");
+  size_t need = sl::transform_workspace_bytes(s, batch);
+  if (with_model) {
+    size_t cnn = 0;
+    int rc = sl_cnn_workspace_size(s, batch, 0, &cnn);
+    if (rc) return rc;
+    // the shrunk coefficients, then whatever the CNN and the inverse need (they
+    // run one after the other on the stream, so they share the rest)
+    need = al256((size_t)batch * s->R * (size_t)s->cfg.npix() * sizeof(float)) +
+           std::max(need, cnn);
+  }
+  *bytes_out = need;
+  return SL_OK;
 }
 
+int sl_denoise(const sl_system *s, const float *x_dev, int batch, const float *sigma_dev,
+               const float *K_host, const sl_shrinkage_model *model, void *coeffs_dev,
+               float *scales_dev, float *out_dev, void *workspace_dev, size_t workspace_bytes,
+               void *stream) {
+  if (!model) {
+    if (!sigma_dev || !K_host) return fail(SL_EINVAL, "sigma_dev and K_host are required");
+    int rc = sl_forward(s, x_dev, batch, coeffs_dev, scales_dev, workspace_dev, workspace_bytes,
+                        stream);
+    if (rc) return rc;
+    return sl_inverse(s, coeffs_dev, scales_dev, batch, sigma_dev, K_host, out_dev, workspace_dev,
+                      workspace_bytes, stream);
+  }
+  // learned shrinkage: forward, gains from the network, inverse of g .* c
+  if (!s) return fail(SL_EINVAL, "system is NULL");
+  if (!sigma_dev || !model->params_dev || !model->packed_dev || !workspace_dev)
+    return fail(SL_EINVAL, "sigma_dev, the model's buffers and the workspace are required");
+  if (batch < 1 || batch > 65535) return fail(SL_EINVAL, "batch must be in 1..65535");
+  size_t need = 0;
+  int rc = sl_denoise_workspace_size(s, batch, 1, &need);
+  if (rc) return rc;
+  if (workspace_bytes < need)
+    return fail(SL_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+  if ((uintptr_t)workspace_dev & 15u) return fail(SL_EINVAL, "workspace must be 16-byte aligned");
+  const size_t shrunk_bytes = al256((size_t)batch * s->R * (size_t)s->cfg.npix() * sizeof(float));
+  float *shrunk = (float *)workspace_dev;
+  void *rest = (char *)workspace_dev + shrunk_bytes;
+  const size_t rest_bytes = workspace_bytes - shrunk_bytes;
+  rc = sl_forward(s, x_dev, batch, coeffs_dev, scales_dev, rest, rest_bytes, stream);
+  if (rc) return rc;
+  rc = sl_cnn_apply(s, model->params_dev, model->packed_dev, (const float *)coeffs_dev,
+                    sigma_dev, batch, shrunk, nullptr, rest, rest_bytes, stream);
+  if (rc) return rc;
+  return sl_inverse(s, shrunk, nullptr, batch, nullptr, nullptr, out_dev, rest, rest_bytes,
+                    stream);
+}
+
+int sl_get_filters(const sl_system *s, double *filters_host) {
+  if (!s || !filters_host) return fail(SL_EINVAL, "NULL argument");
+  slh::Bank bank;
+  std::string err;
+  int rc = s->wavelet ? slh::build_wavelet_bank(s->cfg, bank, filters_host, err)
+                      : slh::build_bank(s->cfg, bank, filters_host, err);
+  if (rc != SL_OK) return fail(rc, err);
+  return SL_OK;
+}
+
+int sl_get_dual_weight(const sl_system *s, double *dual_host) {
+  if (!s || !dual_host) return fail(SL_EINVAL, "NULL argument");
+  slh::Bank bank;
+  std::string err;
+  std::vector<double> tmp;
+  int rc;
+  if (s->wavelet) {
+    // the wavelet bank forms Psi_hat from the filters it writes
+    tmp.resize((size_t)s->R * s->cfg.npix());
+    rc = slh::build_wavelet_bank(s->cfg, bank, tmp.data(), err);
+  } else {
+    rc = slh::build_bank(s->cfg, bank, nullptr, err);
+  }
+  if (rc != SL_OK) return fail(rc, err);
+  std::copy(bank.dual.begin(), bank.dual.end(), dual_host);
+  return SL_OK;
+}
 
 int sl_inpaint_workspace_size(const sl_system *s, int batch, size_t *bytes_out) {
   if (!s || !bytes_out) return fail(SL_EINVAL, "NULL argument");

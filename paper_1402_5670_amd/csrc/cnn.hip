@@ -18,6 +18,7 @@
 // weights; weight gradients put pixels on the reduction axis.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 
 #include "cnn.hpp"
@@ -688,15 +689,18 @@ __global__ void k_pack(const float *__restrict__ params, int J, int layer, int m
   Wp[idx] = f2bf(v);
 }
 
-// Adam (Kingma and Ba) on the FP32 master parameters.
+// Adam (Kingma and Ba) on the FP32 master parameters.  The constants b1,
+// 1 - b1, b2, 1 - b2 and the bias corrections c1 = 1 - b1^t, c2 = 1 - b2^t
+// are formed in double on the host and rounded once (1 - 0.999f in float32
+// would be 1.3e-5 off 0.001).
 __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
-                       float *__restrict__ v, int n, float lr, float b1, float b2, float eps,
-                       float c1, float c2) {
+                       float *__restrict__ v, int n, float lr, float b1, float omb1, float b2,
+                       float omb2, float eps, float c1, float c2) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const float gg = g[k];
-  const float mm = b1 * m[k] + (1.f - b1) * gg;
-  const float vv = b2 * v[k] + (1.f - b2) * gg * gg;
+  const float mm = b1 * m[k] + omb1 * gg;
+  const float vv = b2 * v[k] + omb2 * gg * gg;
   m[k] = mm;
   v[k] = vv;
   p[k] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
@@ -856,11 +860,12 @@ hipError_t cnn_pack(const float *params, int J, int layer, int mode, uint16_t *W
   return hipGetLastError();
 }
 
-hipError_t cnn_adam(float *p, const float *g, float *m, float *v, int n, float lr, float b1,
-                    float b2, float eps, int t, hipStream_t st) {
-  const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
-  hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, st, p, g, m, v, n, lr, b1, b2,
-                     eps, c1, c2);
+hipError_t cnn_adam(float *p, const float *g, float *m, float *v, int n, float lr, double b1,
+                    double b2, double eps, int t, hipStream_t st) {
+  const float c1 = (float)(1.0 - std::pow(b1, (double)t));
+  const float c2 = (float)(1.0 - std::pow(b2, (double)t));
+  hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, st, p, g, m, v, n, lr, (float)b1,
+                     (float)(1.0 - b1), (float)b2, (float)(1.0 - b2), (float)eps, c1, c2);
   return hipGetLastError();
 }
 

@@ -59,8 +59,8 @@ hipError_t cnn_wgrad(const uint16_t *x, const uint16_t *dy, int H, int W, int pl
                      int out_blocks, hipStream_t st);
 hipError_t cnn_pack(const float *params, int J, int layer, int mode, uint16_t *Wp, int NB,
                     hipStream_t st);
-hipError_t cnn_adam(float *p, const float *g, float *m, float *v, int n, float lr, float b1,
-                    float b2, float eps, int t, hipStream_t st);
+hipError_t cnn_adam(float *p, const float *g, float *m, float *v, int n, float lr, double b1,
+                    double b2, double eps, int t, hipStream_t st);
 hipError_t cnn_copy_lowpass(const float *coef, float *coef_out, int B, int R, int HWn,
                             hipStream_t st);
 hipError_t sq_error_grad(const float *a, const float *b, size_t n, float scale, float *out,

@@ -262,7 +262,7 @@ int sl_cnn_adam(float *params_dev, const float *grads_dev, float *m_dev, float *
                 float lr, int step, void *stream) {
   if (!params_dev || !grads_dev || !m_dev || !v_dev || n < 1 || step < 1)
     return sl::set_error(SL_EINVAL, "bad arguments to sl_cnn_adam");
-  CK(sl::cnn_adam(params_dev, grads_dev, m_dev, v_dev, n, lr, 0.9f, 0.999f, 1e-8f, step,
+  CK(sl::cnn_adam(params_dev, grads_dev, m_dev, v_dev, n, lr, 0.9, 0.999, 1e-8, step,
                   (hipStream_t)stream));
   return SL_OK;
 }

@@ -298,9 +298,9 @@ int sl_multi_graph_build(sl_multi *m, int what, const float *const *x_dev,
   if (!m->fork) CK(hipEventCreateWithFlags(&m->fork, hipEventDisableTiming));
   Bufs b{x_dev, coeffs_dev, scales_dev, sigma_dev, K_host, out_dev, (char *)workspace_dev};
   hipStream_t cs = m->side[0];
-  int timing_was = 0;
-  (void)timing_was;
   CK(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+  // per-pass timing events must not be recorded into the graph
+  const bool capturing_was = sl::set_capturing(true);
   int rc = SL_OK;
   hipError_t e = hipEventRecord(m->fork, cs);
   for (int s = 1; s < n && e == hipSuccess; ++s) e = hipStreamWaitEvent(m->side[s], m->fork, 0);
@@ -311,6 +311,7 @@ int sl_multi_graph_build(sl_multi *m, int what, const float *const *x_dev,
       if (e == hipSuccess) e = hipStreamWaitEvent(cs, m->join[s], 0);
     }
   }
+  sl::set_capturing(capturing_was);
   hipGraph_t g = nullptr;
   hipError_t ec = hipStreamEndCapture(cs, &g);
   if (rc) {

@@ -23,6 +23,7 @@ struct sl_system {
   int inv_images = 0;             // images per inverse accumulation block (0 = auto)
   int split_pairs = 1;            // small grids split the pair loop over blocks
   bool plane3d = true;            // volumes: y and x passes of a z-slice in LDS
+  bool wavelet = false;           // built by sl_build_wavelet_system
   float *d_filt = nullptr;    // 2D: [R][H][W]
   float *d_psi = nullptr;     // Psi_hat on the grid
   float *d_l2 = nullptr, *d_l1 = nullptr;
@@ -50,4 +51,7 @@ size_t transform_workspace_bytes(const sl_system *s, int batch);
 // record an error message for sl_last_error and return code
 int set_error(int code, const std::string &msg);
 int hip_error(hipError_t e, const char *what);
+// mark the calling thread as capturing a graph (per-pass timing events are
+// then not recorded); returns the previous state
+bool set_capturing(bool on);
 }

@@ -156,8 +156,15 @@ def test_largest_plane_sampled_parity():
         assert rel(xr[b].cpu().numpy(), xs[b]) < 1e-5
 
 
-@pytest.mark.parametrize("dtype,tol", [("f16", 2e-3), ("bf16", 2e-2)])
-def test_half_storage(dtype, tol):
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_half_storage(dtype):
+    # Coefficients of both 16-bit storage types are held to the 2e-3 budget.
+    # The reconstruction error is bounded by the coefficient error times
+    # sqrt(B / A), A = min Psi_hat and B = max Psi_hat (the frame bounds of
+    # eq. frame_filter): the dual-frame inverse has norm 1 / sqrt(A) and
+    # ||c|| <= sqrt(B) ||x||.  FP16 (11-bit significand) meets 2e-3 after that
+    # amplification; BF16 (8-bit significand, relative rounding error about
+    # 1.7e-3 RMS) is held to the bound itself.
     print(f"case: 384x384 J=3 d=[1,1,2] storage {dtype}", flush=True)
     Bn = 3
     xs = np.stack([syn.noisy_cartoon2d(384, 384, 4001 + b, 0.1)[1] for b in range(Bn)])
@@ -167,11 +174,54 @@ def test_half_storage(dtype, tol):
     xr = sysg.inverse(c, s)
     torch.cuda.synchronize()
     cd = _decode(c, s)
+    amp = np.sqrt(o.dual_weight.max() / o.dual_weight.min())
     for b in range(Bn):
-        assert rel(cd[b], T.forward(xs[b], o.filters)) < tol
-    assert rel(xr.cpu().numpy(), xs) < tol
+        ec = rel(cd[b], T.forward(xs[b], o.filters))
+        ex = rel(xr[b].cpu().numpy(), xs[b])
+        print(f"image {b}: coefficients {ec:.2e}, reconstruction {ex:.2e} "
+              f"(bound {amp * ec + 1e-5:.2e})", flush=True)
+        assert ec < 2e-3
+        assert ex < amp * ec + 1e-5
+        if dtype == "f16":
+            assert ex < 2e-3
     # the stored values stay inside the half-precision range
     assert torch.isfinite(c.float()).all()
+
+
+def _maxflat13():
+    """A user-supplied symmetric 13-tap lowpass (not the library default):
+    H(0) = 1, H(pi) = 0, H''(0) = H(0) = H''(0) = 0, H''(pi) = 0 and
+    H(pi/2) = 1/sqrt(2), with H(w) = h0 + 2 sum_n h_n cos(n w)."""
+    n = np.arange(1, 7, dtype=np.float64)
+    rows = [np.r_[1.0, 2 * np.ones(6)], np.r_[1.0, 2 * (-1.0) ** n], np.r_[0.0, n ** 2],
+            np.r_[0.0, n ** 4], np.r_[0.0, n ** 6], np.r_[0.0, n ** 2 * (-1.0) ** n],
+            np.r_[1.0, 2 * np.cos(n * np.pi / 2)]]
+    half = np.linalg.solve(np.array(rows), [1, 0, 0, 0, 0, 0, 1 / np.sqrt(2)])
+    return np.r_[half[:0:-1], half]
+
+
+@pytest.mark.parametrize("dims,levels,full", [((96, 128), [0, 1, 2], False),
+                                              ((64, 64), [1, 1, 2], True)])
+def test_user_qmf_and_fan_filter(dims, levels, full):
+    # Sections 3.2.2 and 5.1 let the user choose the QMF h and the fan filter P:
+    # a 13-tap h and the K = 3 half-band fan (11 x 11 taps) run through the
+    # device path and match the oracle built from the same taps
+    from oracle import filters as F
+    print(f"case: user h (13 taps) and P (K=3) {dims} J=3 {levels} full={full}", flush=True)
+    h = _maxflat13()
+    P3 = F.fan_filter(3)
+    Bn = 2
+    xs = np.stack([syn.noisy_cartoon2d(*dims, 600 + b, 0.1)[1] for b in range(Bn)])
+    sysg = B.System(dims, 3, levels, full_system=full, qmf=h, dir_filter=P3[0])
+    o = S.build_2d(dims, 3, levels, full, qmf=(h, 6), dir_filter=P3)
+    assert sysg.R == o.filters.shape[0]
+    c, _ = sysg.forward(_gpu(xs))
+    xr = sysg.inverse(c)
+    torch.cuda.synchronize()
+    cn = c.cpu().numpy()
+    for b in range(Bn):
+        assert rel(cn[b], T.forward(xs[b], o.filters)) < 1e-5
+    assert rel(xr.cpu().numpy(), xs) < 1e-5
 
 
 def test_hard_threshold_exact_mask():

@@ -187,3 +187,100 @@ def test_training_reduces_loss():
         losses.append(float(scratch[0].item()) / n)
     assert losses[-1] < 0.9 * losses[0], losses
     assert np.isfinite(losses).all()
+
+
+def test_cnn_forward_multi_tile_matches_oracle():
+    # 128 x 128 planes hold 8 x 4 output tiles of 16 x 32; B = 2 and R = 17 give
+    # 32 detail planes = 1024 tiles on a grid of at most 256 persistent blocks, so
+    # each block runs the prefetch / double-buffer loop over several tiles, and
+    # block b's tiles (b, b + 256, ...) lie in planes b // 32, b // 32 + 8, ...:
+    # the first is a scale-0 plane and the second a scale-1 plane, so the
+    # per-scale weights are reloaded inside the loop.
+    print("case: cnn apply 128x128 J=2 B=2 (1024 tiles, multi-tile loop)", flush=True)
+    sysg, sig, c, params, pg = _setup(dims=(128, 128), seed=11)
+    net = B.Shrinkage(sysg, pg)
+    gains = torch.zeros_like(c)
+    out = net.apply(c, _gpu(sig), gains=gains)
+    torch.cuda.synchronize()
+    cn = c.cpu().numpy().astype(np.float64)
+    gn = gains.cpu().numpy()
+    on = out.cpu().numpy()
+    l2 = np.array([s[4] for s in sysg.subbands], dtype=np.float32)
+    scales_seen = set()
+    worst = 0.0
+    diffs = []
+    for b in range(c.shape[0]):
+        for i in range(1, sysg.R):
+            j = sysg.subbands[i][1]
+            scales_seen.add(j)
+            g, _ = OC.forward(params[j], cn[b, i], float(sig[b]), float(l2[i]), bf16=True)
+            # each plane within 1e-3 relative L2; element-wise (gains lie in (0, 1))
+            # within 5e-3: where float32 and float64 accumulation put an activation
+            # on opposite sides of a bfloat16 rounding boundary, it moves by one
+            # bfloat16 step (2^-8 relative), which reaches the gain scaled by the
+            # next layers' weights and by g (1 - g) <= 1/4
+            d = np.abs(gn[b, i] - g)
+            worst = max(worst, float(np.max(d)))
+            diffs.append(d.ravel())
+            assert rel(gn[b, i], g) < 1e-3, (b, i, rel(gn[b, i], g))
+            assert np.allclose(on[b, i], gn[b, i] * cn[b, i], rtol=1e-6, atol=1e-7)
+    q = np.quantile(np.concatenate(diffs), [0.5, 0.99, 0.999])
+    print(f"|gain - oracle|: median {q[0]:.1e}, 99% {q[1]:.1e}, 99.9% {q[2]:.1e}, "
+          f"max {worst:.2e}", flush=True)
+    assert worst < 5e-3
+    assert scales_seen == {0, 1}
+
+
+def test_adam_matches_oracle_over_steps():
+    # sl_cnn_adam against the oracle's Adam (float64) over five steps with
+    # changing gradients and learning rates; from step 2 on beta1 and beta2 enter
+    # the moments differently, so the comparison covers the recurrences and the
+    # bias corrections, not just the first step
+    print("case: adam 5 steps, 2 x 10145 parameters", flush=True)
+    from oracle import cnn as OCN
+    rng = np.random.default_rng(21)
+    n = 2 * B.CNN_PARAMS
+    p0 = rng.standard_normal(n) * 0.1
+    pg = _gpu(p0)
+    m = torch.zeros_like(pg)
+    v = torch.zeros_like(pg)
+    ref = {"w": p0.astype(np.float32).astype(np.float64)}
+    st = {}
+    for t in range(1, 6):
+        g = rng.standard_normal(n) * (0.5 ** t) + 0.01 * t
+        lr = 1e-3 * (1.0 + 0.25 * t)
+        g32 = g.astype(np.float32)
+        B.adam_step(pg, _gpu(g32), m, v, lr, t)
+        OCN.adam_step(ref, {"w": g32.astype(np.float64)}, st, lr=np.float32(lr))
+        torch.cuda.synchronize()
+        got_p = pg.cpu().numpy().astype(np.float64)
+        got_m = m.cpu().numpy().astype(np.float64)
+        got_v = v.cpu().numpy().astype(np.float64)
+        assert rel(got_m, st["m_w"]) < 1e-6, (t, rel(got_m, st["m_w"]))
+        assert rel(got_v, st["v_w"]) < 1e-6, (t, rel(got_v, st["v_w"]))
+        assert rel(got_p, ref["w"]) < 1e-6, (t, rel(got_p, ref["w"]))
+        # the accumulated update itself (not only the parameters, which it barely moves)
+        upd_got = got_p - p0.astype(np.float32)
+        upd_ref = ref["w"] - p0.astype(np.float32)
+        assert rel(upd_got, upd_ref) < 1e-4, (t, rel(upd_got, upd_ref))
+
+
+@pytest.mark.parametrize("n", [1, 1000, 256 * 1024 + 37])
+def test_sq_error_grad_matches_float64(n):
+    # out = scale (a - b) and loss = sum (a - b)^2 against float64 sums of the same
+    # float32 inputs; n = 1 and a ragged n exercise the grid-stride loop's ends
+    print(f"case: sq_error_grad n={n}", flush=True)
+    rng = np.random.default_rng(n)
+    a = rng.standard_normal(n).astype(np.float32)
+    b = (a + rng.standard_normal(n) * 0.1).astype(np.float32)
+    scale = 2.0 / n
+    out = torch.empty(n, dtype=torch.float32, device=DEV)
+    scratch = torch.full((B.SQERR_SCRATCH,), 7.0, dtype=torch.float32, device=DEV)
+    B.sq_error_grad(_gpu(a), _gpu(b), scale, out, scratch)
+    torch.cuda.synchronize()
+    d = a.astype(np.float64) - b.astype(np.float64)
+    ref_out = np.float32(scale) * d
+    assert rel(out.cpu().numpy(), ref_out) < 1e-6
+    loss = float(scratch[0].item())
+    ref_loss = float(np.sum(d * d))
+    assert abs(loss - ref_loss) < 1e-5 * ref_loss, (loss, ref_loss)

@@ -45,7 +45,7 @@ def _gpu(x):
 
 @pytest.mark.parametrize("dims,J,Bn,dtype,tol", [
     ((64, 64), 3, 2, "f32", 1e-5), ((24, 96), 2, 3, "f32", 1e-5), ((512, 512), 4, 1, "f32", 1e-5),
-    ((128, 128), 3, 2, "f16", 2e-3), ((128, 128), 3, 2, "bf16", 2e-2)])
+    ((128, 128), 3, 2, "f16", 2e-3), ((128, 128), 3, 2, "bf16", 2e-3)])
 def test_wavelet_system_parity(dims, J, Bn, dtype, tol):
     print(f"case: wavelet system {dims} J={J} B={Bn} {dtype}", flush=True)
     x = np.random.default_rng(51).standard_normal((Bn, *dims))
@@ -58,9 +58,16 @@ def test_wavelet_system_parity(dims, J, Bn, dtype, tol):
     cg = c.float().cpu().numpy().astype(np.float64)
     if dtype != "f32":
         cg = cg * sc.cpu().numpy().astype(np.float64)[:, :, None, None]
+    # coefficients within tol; the reconstruction within tol, or for BF16 within
+    # the coefficient error times sqrt(B / A) (frame bounds A = min Psi_hat,
+    # B = max Psi_hat: the dual-frame inverse has norm 1 / sqrt(A), ||c|| <=
+    # sqrt(B) ||x||)
+    amp = np.sqrt(o.dual_weight.max() / o.dual_weight.min())
     for b in range(Bn):
-        assert rel(cg[b], T.forward(x[b], o.filters)) < tol
-    assert rel(xr.cpu().numpy(), x) < tol
+        ec = rel(cg[b], T.forward(x[b], o.filters))
+        ex = rel(xr[b].cpu().numpy(), x[b])
+        assert ec < tol
+        assert ex < (amp * ec + 1e-5 if dtype == "bf16" else tol), (ec, ex, amp)
 
 
 def _sigma32(dinit, delta_min, iterations, t):

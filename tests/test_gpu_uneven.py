@@ -83,6 +83,32 @@ def test_uneven_eager_and_graph():
         torch.cuda.synchronize()
 
 
+def test_uneven_graph_build_with_timing_on():
+    # building the multi-batch graph while per-pass timing is on records no
+    # timing events into the graph: after replays the timing queries return the
+    # eager launches only, and the replayed results are unchanged
+    print("case: uneven graph build with pass timing enabled", flush=True)
+    m, systems, host, xs, coeffs, scales, outs, ws = _setup()
+    B.timing_reset()
+    B.timing_enable(True)
+    try:
+        m.graph_build(3, xs, coeffs, scales, outs=outs, workspace=ws)
+        for _ in range(2):
+            m.graph_launch()
+        torch.cuda.synchronize()
+        assert B.timing_report() == {}
+        m.run(1, xs, coeffs, scales, workspace=ws)
+        torch.cuda.synchronize()
+        rep = B.timing_report()
+        assert rep and all(n > 0 and ms >= 0 for ms, n in rep.values())
+    finally:
+        B.timing_enable(False)
+        B.timing_reset()
+    m.graph_launch()
+    torch.cuda.synchronize()
+    _check(systems, host, coeffs, scales, outs, 2e-3)
+
+
 def test_uneven_autotune(tmp_path):
     print("case: uneven autotune", flush=True)
     m, systems, host, xs, coeffs, scales, outs, ws = _setup()

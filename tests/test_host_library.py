@@ -39,7 +39,7 @@ def test_exports_every_declared_symbol():
     for name in declared:
         assert hasattr(lib, name), name
     assert set(B.exported_symbols()) <= set(declared)
-    assert lib.sl_abi_version() == 1
+    assert lib.sl_abi_version() == 2
 
 
 @pytest.mark.parametrize("dims,J,levels,full", [
@@ -120,6 +120,14 @@ def test_error_codes():
     assert _lib().sl_config_num_subbands(ctypes.byref(cfg), ctypes.byref(R)) == -1
     assert b"ndim" in _lib().sl_last_error()
     assert _lib().sl_config_num_subbands(None, ctypes.byref(R)) == -1
+    # calls on a built system reject a NULL system or buffer before any GPU work
+    n = ctypes.c_size_t()
+    buf = (ctypes.c_double * 4)()
+    assert _lib().sl_get_filters(None, buf) == -1
+    assert _lib().sl_get_dual_weight(None, buf) == -1
+    assert _lib().sl_denoise_workspace_size(None, 1, 1, ctypes.byref(n)) == -1
+    assert _lib().sl_denoise(None, None, 1, None, None, None, None, None, None, None, 0,
+                             None) == -1
 
 
 def test_missing_library_fails_loudly(tmp_path):
