@@ -201,6 +201,25 @@ int sl_denoise_fused(const sl_system *s, const float *x_dev, int batch, const fl
                      const float *K_host, float *out_dev, void *workspace_dev,
                      size_t workspace_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and kernels as sl_denoise_fused, with the workspace taken from
+ * a static device array of SL_NOALLOC_SCRATCH_BYTES (128 MiB) that the
+ * library holds on every GPU it runs on until the process ends, instead of a
+ * caller buffer.  Allocates nothing.  The call needs sl_workspace_size(s, B)
+ * <= SL_NOALLOC_SCRATCH_BYTES (one 512 x 512 image with R = 49 fits; larger
+ * batches need a smaller chunk, sl_system_set_chunk_bytes) and returns
+ * SL_ENOMEM otherwise, before any GPU work.  Every call on a GPU shares that
+ * GPU's array: calls that overlap on one GPU (several streams or threads)
+ * race and must be serialised by the caller.  Nothing in the array needs to
+ * start at zero; it keeps the last call's contents.  Arguments and other
+ * errors as for sl_denoise_fused; must be called with the system's device
+ * current.                                                                  */
+#define SL_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int sl_denoise_fused_noalloc(const sl_system *s, const float *x_dev, int batch,
+                             const float *sigma_dev, const float *K_host, float *out_dev,
+                             void *stream);
+
 /* Inpainting by iterative hard thresholding (Algorithm 3; Section 5, image
  * and video inpainting).  From f = 0 and with the mask M (1 = known sample),
  * iteration t = 0..iterations-1 computes

@@ -78,6 +78,9 @@ _SIGS = {
     "sl_denoise_workspace_size": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                    ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "sl_get_filters": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "sl_denoise_fused_noalloc": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+                                 ctypes.c_int),
     "sl_get_dual_weight": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "sl_denoise_fused": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
@@ -406,6 +409,19 @@ class System:
                                ctypes.cast(Kh, ctypes.c_void_p) if Kh is not None else None,
                                mp, _ptr(coeffs), _ptr(scales), _ptr(out), _ptr(ws), ws.numel(),
                                _stream()))
+        return out
+
+    def denoise_fused_noalloc(self, x, sigma, K, out=None):
+        """sl_denoise_fused on the library's static scratch array (no workspace)."""
+        import torch
+        self._check_x(x)
+        B = x.shape[0]
+        if out is None:
+            out = torch.empty_like(x)
+        Kh = (ctypes.c_float * len(K))(*[float(k) for k in K])
+        check(lib().sl_denoise_fused_noalloc(self._h, _ptr(x), B, _ptr(sigma),
+                                             ctypes.cast(Kh, ctypes.c_void_p), _ptr(out),
+                                             _stream()))
         return out
 
     def denoise_fused(self, x, sigma, K, out=None, workspace=None):
