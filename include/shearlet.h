@@ -304,6 +304,23 @@ size_t sl_system_chunk_bytes(const sl_system *s);
 int sl_system_set_block_shape(sl_system *s, int inv_images, int split_pairs);
 int sl_system_block_shape(const sl_system *s, int *inv_images, int *split_pairs);
 
+/* XCD-cooperative passes (2D, 512 x 512, SL_F32, batches of at least 8, on a
+ * device of 8 XCDs x 32 compute units).  The 32 workgroups of each XCD
+ * transform one image at a time and exchange every subband-pair plane
+ * between the column and row FFTs through a scratch plane kept in that XCD's
+ * L2, instead of through HBM; results agree with the line passes to float32
+ * rounding (Algorithms 1 and 2 are computed the same way).  With enable = 1
+ * (or $SL_XCD=1 at system build) sl_forward and sl_inverse take them where
+ * supported; the default is 0, the line passes, which measured faster on
+ * MI355X (32 x 512^2, R = 49: 2.35 against 2.67 ms per forward + inverse).
+ * Their waits for the other workgroups of an XCD are bounded by spin_limit
+ * polls (0 = the default, about 2^20); a wait that gives up aborts the pass
+ * (invalid results) and the next call on the system returns SL_EHIP.
+ * sl_system_xcd_active tells whether a call with this batch and a workspace
+ * of sl_workspace_size bytes runs them.  SL_EINVAL for bad arguments.        */
+int sl_system_set_xcd(sl_system *s, int enable, int spin_limit);
+int sl_system_xcd_active(const sl_system *s, int batch, int *active);
+
 /* ---- uneven batches (several image sizes in one schedule) ----------------
  * The forward (and inverse) transform of a batch of images of different
  * sizes: sl_multi_run with what = 1 is the uneven-batch forward call

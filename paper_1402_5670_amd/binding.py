@@ -124,6 +124,9 @@ _SIGS = {
     "sl_system_set_chunk_bytes": ([ctypes.c_void_p, ctypes.c_size_t], ctypes.c_int),
     "sl_system_chunk_bytes": ([ctypes.c_void_p], ctypes.c_size_t),
     "sl_system_set_block_shape": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "sl_system_set_xcd": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "sl_system_xcd_active": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
+                             ctypes.c_int),
     "sl_system_block_shape": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
                                ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "sl_multi_create": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
@@ -468,6 +471,16 @@ class System:
                                  _ptr(f0), _ptr(f1), 1 if use_graph else 0, _ptr(workspace),
                                  workspace.numel(), _stream()))
         return f0, f1
+
+    def set_xcd(self, enable=True, spin_limit=0):
+        """Turn the XCD-cooperative 2D passes on or off (off by default;
+        spin_limit: polls before a wait gives up, 0 = default)."""
+        check(lib().sl_system_set_xcd(self._h, int(bool(enable)), int(spin_limit)))
+
+    def xcd_active(self, batch):
+        a = ctypes.c_int()
+        check(lib().sl_system_xcd_active(self._h, int(batch), ctypes.byref(a)))
+        return bool(a.value)
 
     def set_block_shape(self, inv_images=0, split_pairs=1):
         """Schedule choice of the 2D column passes (sl_system_set_block_shape)."""

@@ -17,7 +17,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libshearlet.so")
 
 SOURCES = ["api.cpp", "host_filters.cpp", "kernels2d.hip", "kernels3d.hip", "cnn.hip",
-           "cnn_api.cpp", "render.hip", "multi_api.cpp", "inpaint.hip", "noalloc.hip"]
+           "cnn_api.cpp", "render.hip", "multi_api.cpp", "inpaint.hip", "noalloc.hip",
+           "xcd2d.hip"]
 
 ARCH = os.environ.get("SL_OFFLOAD_ARCH", "gfx950")
 

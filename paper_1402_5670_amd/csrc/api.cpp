@@ -143,6 +143,15 @@ sl::Sys2D view2d(const sl_system *s) {
   return view2d(s, H, W, H, W);
 }
 
+// The XCD-cooperative passes replace the line passes of a 2D forward or
+// inverse when the device and shape support them and the chunk region of the
+// workspace can hold their scratch planes.
+bool use_xcd(const sl_system *s, int B, const Layout &L) {
+  if (!s->xcd || s->cfg.ndim != 2 || !s->xcd_err_dev) return false;
+  if (L.off_xmax - L.off_chunk < sl::xcd_scratch_bytes()) return false;
+  return sl::xcd_supported(view2d(s), B);
+}
+
 int inv_groups(const sl_system *s, int B) {
   if (s->cfg.ndim != 2) return 1;
   int nb, np;
@@ -176,6 +185,12 @@ int check_call(const sl_system *s, int batch, const void *a, const void *b, void
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != s->device)
     return fail(SL_EINVAL, "the current HIP device is not the system's device");
+  if (s->xcd_err_host && *(volatile int *)s->xcd_err_host) {
+    *(volatile int *)s->xcd_err_host = 0;
+    return fail(SL_EHIP,
+                "an XCD-cooperative pass of an earlier call gave up waiting for its workgroups; "
+                "the results of that call are invalid");
+  }
   return SL_OK;
 }
 
@@ -196,11 +211,14 @@ enum Pass {
   P_ROWS_REAL_IFFT,
   P_AUX,
   P_ROWS_THR,
+  P_XCD_FWD,
+  P_XCD_INV,
   P_COUNT
 };
 const char *kPassNames[P_COUNT] = {"rows_real_fft",   "cols_fft",      "cols_filter_ifft",
                                    "rows_coef",       "rows_coef_fft", "cols_fft_acc",
-                                   "rows_real_ifft",  "aux",           "rows_thr"};
+                                   "rows_real_ifft",  "aux",           "rows_thr",
+                                   "xcd_fwd",         "xcd_inv"};
 
 struct Timing {
   bool on = false;
@@ -677,6 +695,21 @@ int build_system_impl(const sl_config *cfg, bool wavelet, sl_system **out) {
       return rc;
     }
   }
+  if (!is3d) {
+    // flag that a timed-out cooperative wait sets (host memory the kernel
+    // writes directly); without it the cooperative passes stay off
+    void *hp = nullptr, *dp = nullptr;
+    // off by default: on MI355X the line passes are faster (32 x 512^2 step
+    // 2.35 ms against 2.67 ms with the cooperative passes)
+    const char *xe = std::getenv("SL_XCD");
+    s->xcd = xe ? std::atoi(xe) != 0 : 0;
+    if (hipHostMalloc(&hp, 64, hipHostMallocCoherent) == hipSuccess) {
+      s->xcd_err_host = (int *)hp;
+      *(volatile int *)s->xcd_err_host = 0;
+      if (hipHostGetDevicePointer(&dp, hp, 0) == hipSuccess) s->xcd_err_dev = (int *)dp;
+    }
+    (void)hipGetLastError();
+  }
   for (int a = 0; a < s->cfg.ndim; ++a) {
     int N = (int)s->cfg.dims[a];
     if (s->d_tw.count(N)) continue;
@@ -734,6 +767,7 @@ void sl_free_system(sl_system *s) {
     (void)hipGraphDestroy(g.graph);
   }
   for (void *p : s->allocs) (void)hipFree(p);
+  if (s->xcd_err_host) (void)hipHostFree(s->xcd_err_host);
   delete s;
 }
 
@@ -748,6 +782,20 @@ int sl_system_subband(const sl_system *s, int i, sl_subband *out) {
   if (i < 0 || i >= s->R) return fail(SL_EINVAL, "subband index out of range");
   const auto &b = s->subs[i];
   *out = {b.cone, b.j, b.k1, b.k2, s->l2[i], s->l1[i]};
+  return SL_OK;
+}
+
+int sl_system_set_xcd(sl_system *s, int enable, int spin_limit) {
+  if (!s || (enable != 0 && enable != 1) || spin_limit < 0)
+    return fail(SL_EINVAL, "enable must be 0 or 1 and spin_limit >= 0");
+  s->xcd = enable;
+  s->xcd_spin = spin_limit ? spin_limit : (1 << 20);
+  return SL_OK;
+}
+
+int sl_system_xcd_active(const sl_system *s, int batch, int *active) {
+  if (!s || !active || batch < 1) return fail(SL_EINVAL, "bad arguments");
+  *active = use_xcd(s, batch, layout(s, batch)) ? 1 : 0;
   return SL_OK;
 }
 
@@ -774,6 +822,12 @@ static int forward_impl(const sl_system *s, const float *x_dev, int batch, void 
   if (s->cfg.ndim == 3)
     return forward3d(s, x_dev, batch, coeffs_dev, scales_dev, F, T, xmax, dual, st);
   const sl::Sys2D v = view2d(s);
+  if (!dual && use_xcd(s, batch, L)) {
+    SL_LAUNCH(P_XCD_FWD, st,
+              sl::launch_xcd_fwd(v, x_dev, (float *)coeffs_dev, ws + L.off_chunk,
+                                 s->xcd_err_dev, batch, s->xcd_spin, st));
+    return SL_OK;
+  }
   if (scaled) SL_LAUNCH(P_AUX, st, sl::launch_zero_u32(xmax, batch, st));
   SL_LAUNCH(P_ROWS_REAL_FFT, st, sl::launch_rows_real_fft(v, x_dev, F, scaled ? xmax : nullptr, batch, st));
   SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(v, F, F, batch, false, st));
@@ -827,6 +881,12 @@ int sl_inverse(const sl_system *s, const void *coeffs_dev, const float *scales_d
   float2 *U = (float2 *)(ws + L.off_chunk);
   if (s->cfg.ndim == 3) return inverse3d(s, coeffs_dev, scales_dev, batch, thr, x_dev, ACC, U, st);
   const sl::Sys2D v = view2d(s);
+  if (use_xcd(s, batch, L)) {
+    SL_LAUNCH(P_XCD_INV, st,
+              sl::launch_xcd_inv(v, (const float *)coeffs_dev, thr, x_dev, ws + L.off_chunk,
+                                 s->xcd_err_dev, batch, s->xcd_spin, st));
+    return SL_OK;
+  }
   int nb, np;
   chunk_plan(s, batch, nb, np);
   const int P = (s->R + 1) / 2;

@@ -96,6 +96,21 @@ hipError_t launch_cols_acc_finish(const Sys2D &s, float2 *ACC, const float2 *par
 // ACC -> x (row inverse DFT, real part, 1/(HW))
 hipError_t launch_rows_real_ifft(const Sys2D &s, const float2 *V, float *x, int B, hipStream_t st);
 
+// ---- XCD-cooperative passes (xcd2d.hip) --------------------------------------
+// 512 x 512 planes, float32 coefficients: the 32 workgroups of each XCD
+// transform one image at a time and exchange every plane through a scratch
+// plane in the XCD's L2.  scratch holds xcd_scratch_bytes() (8 planes and 8
+// counter lines); err (host-visible, may be null) is set when a bounded wait
+// gives up, in which case the results are invalid.
+bool xcd_supported(const Sys2D &s, int B);
+size_t xcd_scratch_bytes();
+// x -> coefficients (Algorithm 1)
+hipError_t launch_xcd_fwd(const Sys2D &s, const float *x, float *coef, void *scratch, int *err,
+                          int B, int spin, hipStream_t st);
+// coefficients (hard threshold on load if thr.sigma) -> x (Algorithm 2)
+hipError_t launch_xcd_inv(const Sys2D &s, const float *coef, const ThrArgs &thr, float *x,
+                          void *scratch, int *err, int B, int spin, hipStream_t st);
+
 // ---- 3D --------------------------------------------------------------------
 // Filter of one subband generated from its factors (see kernels3d.hip):
 //   lowpass (cone 0): tab[g_off + x] * tab[p1_off + y] * tab[p2_off + z]

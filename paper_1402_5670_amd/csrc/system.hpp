@@ -24,6 +24,10 @@ struct sl_system {
   int split_pairs = 1;            // small grids split the pair loop over blocks
   bool plane3d = true;            // volumes: y and x passes of a z-slice in LDS
   bool wavelet = false;           // built by sl_build_wavelet_system
+  int xcd = 0;                    // 2D: XCD-cooperative passes where supported
+  int xcd_spin = 1 << 20;         // polls before a cooperative wait gives up
+  int *xcd_err_host = nullptr;    // host-visible flag a timed-out wait sets
+  int *xcd_err_dev = nullptr;     // its device address
   float *d_filt = nullptr;    // 2D: [R][H][W]
   float *d_psi = nullptr;     // Psi_hat on the grid
   float *d_l2 = nullptr, *d_l1 = nullptr;
