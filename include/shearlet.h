@@ -304,6 +304,18 @@ size_t sl_system_chunk_bytes(const sl_system *s);
 int sl_system_set_block_shape(sl_system *s, int inv_images, int split_pairs);
 int sl_system_block_shape(const sl_system *s, int *inv_images, int *split_pairs);
 
+/* Line plan of the 2D passes (a schedule choice; results are the same up to
+ * float32 rounding order): values_factor 1 (default) or 2, the number of
+ * values each thread holds relative to the default plan.  With 2, the
+ * coefficient row passes transform a 1024-point row with one wavefront (16
+ * values per thread, radix exchanges without block barriers) instead of
+ * two, and the inverse accumulation transforms 1024-point columns with 64
+ * threads each in 512-thread blocks; other lengths and passes keep the
+ * default plan.  Autotuned per size class by sl_multi_autotune.  SL_EINVAL
+ * for other values.                                                         */
+int sl_system_set_line_plan(sl_system *s, int values_factor);
+int sl_system_line_plan(const sl_system *s, int *values_factor);
+
 /* XCD-cooperative passes (2D, 512 x 512, SL_F32, batches of at least 8, on a
  * device of 8 XCDs x 32 compute units).  The 32 workgroups of each XCD
  * transform one image at a time and exchange every subband-pair plane
@@ -345,9 +357,10 @@ int sl_multi_run(sl_multi *m, int what, const float *const *x_dev, void *const *
  * keeps the fastest: chunk sizes of 32..2048 MiB that fit the class's
  * current workspace slot and, for 2D classes, the block shape of
  * sl_system_set_block_shape (one or two images per inverse-accumulation
- * block, pair-loop split on or off).  Cached by size, R, batch and storage
- * type in the text file cache_path, if given (one line per class: key,
- * chunk bytes, images per block, split).                                    */
+ * block, pair-loop split on or off) and, for classes with 1024-point lines,
+ * the line plan of sl_system_set_line_plan.  Cached by size, R, batch and
+ * storage type in the text file cache_path, if given (one line per class:
+ * key, chunk bytes, images per block, split, line plan).                    */
 int sl_multi_autotune(sl_multi *m, const float *const *x_dev, void *const *coeffs_dev,
                       float *const *scales_dev, float *const *out_dev, void *workspace_dev,
                       size_t workspace_bytes, const char *cache_path, void *stream);

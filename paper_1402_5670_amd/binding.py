@@ -125,6 +125,8 @@ _SIGS = {
     "sl_system_chunk_bytes": ([ctypes.c_void_p], ctypes.c_size_t),
     "sl_system_set_block_shape": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "sl_system_set_xcd": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "sl_system_set_line_plan": ([ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
+    "sl_system_line_plan": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "sl_system_xcd_active": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
                              ctypes.c_int),
     "sl_system_block_shape": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
@@ -471,6 +473,15 @@ class System:
                                  _ptr(f0), _ptr(f1), 1 if use_graph else 0, _ptr(workspace),
                                  workspace.numel(), _stream()))
         return f0, f1
+
+    def set_line_plan(self, values_factor):
+        """Values per thread of the 1024-point line FFTs: 1 (default) or 2."""
+        check(lib().sl_system_set_line_plan(self._h, int(values_factor)))
+
+    def line_plan(self):
+        v = ctypes.c_int()
+        check(lib().sl_system_line_plan(self._h, ctypes.byref(v)))
+        return v.value
 
     def set_xcd(self, enable=True, spin_limit=0):
         """Turn the XCD-cooperative 2D passes on or off (off by default;

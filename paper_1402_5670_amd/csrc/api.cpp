@@ -133,6 +133,7 @@ sl::Sys2D view2d(const sl_system *s, int H, int W, int nH, int nW) {
   v.num_cu = s->num_cu;
   v.inv_images = s->inv_images;
   v.split_pairs = s->split_pairs;
+  v.line_em = s->line_em;
   v.twH = nH ? s->d_tw.at(nH) : nullptr;
   v.twW = nW ? s->d_tw.at(nW) : nullptr;
   return v;
@@ -782,6 +783,19 @@ int sl_system_subband(const sl_system *s, int i, sl_subband *out) {
   if (i < 0 || i >= s->R) return fail(SL_EINVAL, "subband index out of range");
   const auto &b = s->subs[i];
   *out = {b.cone, b.j, b.k1, b.k2, s->l2[i], s->l1[i]};
+  return SL_OK;
+}
+
+int sl_system_set_line_plan(sl_system *s, int values_factor) {
+  if (!s || (values_factor != 1 && values_factor != 2))
+    return fail(SL_EINVAL, "values_factor must be 1 or 2");
+  s->line_em = values_factor;
+  return SL_OK;
+}
+
+int sl_system_line_plan(const sl_system *s, int *values_factor) {
+  if (!s || !values_factor) return fail(SL_EINVAL, "NULL argument");
+  *values_factor = s->line_em;
   return SL_OK;
 }
 

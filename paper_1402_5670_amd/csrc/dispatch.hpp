@@ -25,6 +25,8 @@ struct Sys2D {
   int inv_images;           // images per inverse accumulation block: 0 = by
                             // batch (2, or 1 for a single image), or 1 / 2
   int split_pairs;          // 1: small grids split the pair loop over blocks
+  int line_em;              // line plan of the coefficient row passes: 1, or 2
+                            // (twice the values per thread) for 1024-point rows
   const float *filt;        // [R][H][W]
   const float *psi;         // [H][W]  Psi_hat
   const float *l1;          // [R]

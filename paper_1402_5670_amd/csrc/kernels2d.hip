@@ -32,14 +32,29 @@ namespace sl {
 #ifndef SL_COL_EMUL
 #define SL_COL_EMUL 1
 #endif
-template <int N>
+// EM (line plan): each thread holds EM times the plan's values, so a line
+// takes EM times fewer threads (EM = 2 makes a 1024-point row one wavefront,
+// whose radix exchanges need no block barrier); the coefficient row passes
+// take it per system (sl_system_set_line_plan, autotuned for uneven
+// batches), and so does the inverse accumulation of 1024-point columns
+// (launch_cols_fft_acc); the other column passes keep EM = 1.
+template <int N, int EM = 1>
 struct Tile {
-  using PL = Plan<N>;
+  using PL = Plan<N, EM>;
   static constexpr int NT = PL::NT;
   static constexpr int E = PL::E;
   static constexpr int M = NT >= 128 ? 8 : 16;     // lines per block
   static constexpr int THREADS = M * NT;
 };
+// row FFT of a Tile line: wavefront-local exchanges when the line fits a wave
+template <int N, int EM, bool INV>
+__device__ __forceinline__ void row_fft(float2 (&v)[(Tile<N, EM>::E)], int t, const LdsLine &lds,
+                                        const float2 *__restrict__ tw) {
+  fft_line_p<Plan<N, EM>, INV, wave_lines<Plan<N, EM>::NT>()>(v, t, lds, tw);
+}
+// line plans with EM = 2 exist for these lengths
+template <int N>
+constexpr bool em2_length() { return N == 1024; }
 template <int N>
 struct CTile {
   static constexpr int EM = (N >= 256 && N <= 512) ? SL_COL_EMUL : 1;
@@ -279,12 +294,13 @@ k_cols_filter_ifft(const float2 *__restrict__ F, const float *__restrict__ filt,
 // iteration).  Forcing more waves per SIMD (amdgpu_waves_per_eu) spills
 // registers.
 constexpr int kFwdWide = 16, kFwdNarrow = 8;
-template <int N, int MW>
+template <int N, int MW, int EM = 1>
 struct FTile {
-  using PL = Plan<N>;
+  using PL = Plan<N, EM>;
   static constexpr int NT = PL::NT;
   static constexpr int E = PL::E;
-  static constexpr int M = CTile<N>::M < MW ? CTile<N>::M : MW;
+  static constexpr int MC = EM == 1 ? CTile<N>::M : (NT * 16 <= 1024 ? 16 : 8);
+  static constexpr int M = MC < MW ? MC : MW;
   static constexpr int THREADS = M * NT;
 };
 
@@ -293,13 +309,13 @@ __device__ __forceinline__ void stage_twiddles(float2 *twl, const float2 *__rest
   for (int i = threadIdx.x; i < N; i += blockDim.x) twl[i] = tw[i];
 }
 
-template <int N, int BT, int MW>
-__global__ void __launch_bounds__((FTile<N, MW>::THREADS))
+template <int N, int BT, int MW, int EM = 1>
+__global__ void __launch_bounds__((FTile<N, MW, EM>::THREADS))
 k_cols_filter_ifft3(const float2 *__restrict__ F, const float *__restrict__ filt,
                     float2 *__restrict__ T, int W, int R, int b0, int nb, int p0, int np,
                     const float2 *__restrict__ tw) {
-  constexpr int NT = FTile<N, MW>::NT, M = FTile<N, MW>::M, E = FTile<N, MW>::E;
-  using PL = typename FTile<N, MW>::PL;
+  constexpr int NT = FTile<N, MW, EM>::NT, M = FTile<N, MW, EM>::M, E = FTile<N, MW, EM>::E;
+  using PL = typename FTile<N, MW, EM>::PL;
   __shared__ float2 lds[M * N];
   __shared__ float2 twl[N];
   stage_twiddles<N>(twl, tw);       // the FFT's leading barrier orders it
@@ -433,12 +449,12 @@ k_cols_fft_acc3(const float2 *__restrict__ U, const float *__restrict__ filt,
   }
 }
 
-template <int N, int DT>
-__global__ void __launch_bounds__(Tile<N>::THREADS)
+template <int N, int DT, int EM = 1>
+__global__ void __launch_bounds__((Tile<N, EM>::THREADS))
 k_rows_coef(const float2 *__restrict__ T, typename Store<DT>::T *__restrict__ coef,
             const float *__restrict__ scales, int H, int R, int b0, int p0, int np, float inv_hw,
             const float2 *__restrict__ tw) {
-  constexpr int NT = Tile<N>::NT, M = Tile<N>::M, E = Tile<N>::E;
+  constexpr int NT = Tile<N, EM>::NT, M = Tile<N, EM>::M, E = Tile<N, EM>::E;
   __shared__ float2 lds[M * row_lds_len<N>()];
   const int t = threadIdx.x % NT, m = threadIdx.x / NT;
   const int row = blockIdx.x * M + m;
@@ -451,7 +467,7 @@ k_rows_coef(const float2 *__restrict__ T, typename Store<DT>::T *__restrict__ co
   float2 v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = Ti[t + e * NT];
-  fft_line<N, true>(v, t, LdsLine{lds + m * row_lds_len<N>(), 0}, tw);
+  row_fft<N, EM, true>(v, t, LdsLine{lds + m * row_lds_len<N>(), 0}, tw);
   if (!ok) return;
   float sa = inv_hw, sb = inv_hw;
   if (DT != 0) {
@@ -472,13 +488,13 @@ k_rows_coef(const float2 *__restrict__ T, typename Store<DT>::T *__restrict__ co
 // k_rows_coef with the row-group loop and next-row prefetch of k_rows_thr,
 // used for 16-bit storage, whose stores are half as long (32 x 512^2 FP16:
 // step 2.29 -> 2.21 ms; with FP32 coefficients it was 4% slower)
-template <int N, int DT>
-__global__ void __launch_bounds__(Tile<N>::THREADS / 2 > 0 ? Tile<N>::THREADS / 2 : 1)
+template <int N, int DT, int EM = 1>
+__global__ void __launch_bounds__((Tile<N, EM>::THREADS / 2 > 0 ? Tile<N, EM>::THREADS / 2 : 1))
 k_rows_coef_pf(const float2 *__restrict__ T, typename Store<DT>::T *__restrict__ coef,
                const float *__restrict__ scales, int H, int R, int b0, int p0, int np,
                float inv_hw, const float2 *__restrict__ tw) {
-  constexpr int NT = Tile<N>::NT, E = Tile<N>::E;
-  constexpr int M = Tile<N>::M / 2 > 0 ? Tile<N>::M / 2 : 1;
+  constexpr int NT = Tile<N, EM>::NT, E = Tile<N, EM>::E;
+  constexpr int M = Tile<N, EM>::M / 2 > 0 ? Tile<N, EM>::M / 2 : 1;
   __shared__ float2 lds[M * row_lds_len<N>()];
   const int t = threadIdx.x % NT, m = threadIdx.x / NT;
   const int pp = blockIdx.y, bl = blockIdx.z, b = b0 + bl;
@@ -507,7 +523,7 @@ k_rows_coef_pf(const float2 *__restrict__ T, typename Store<DT>::T *__restrict__
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = nx[e];
     if (rg + G < nrg) load(rg + G);
-    fft_line<N, true>(v, t, LdsLine{lds + m * row_lds_len<N>(), 0}, tw);
+    row_fft<N, EM, true>(v, t, LdsLine{lds + m * row_lds_len<N>(), 0}, tw);
     const int row = rg * M + m;
     if (row < H) {
       Raw *ca = ca0 + (size_t)row * N;
@@ -550,12 +566,12 @@ __global__ void k_zero_u32(unsigned *p, int n) {
 // ---------------------------------------------------------------------------
 // inverse
 // ---------------------------------------------------------------------------
-template <int N, int DT>
-__global__ void __launch_bounds__(Tile<N>::THREADS)
+template <int N, int DT, int EM = 1>
+__global__ void __launch_bounds__((Tile<N, EM>::THREADS))
 k_rows_coef_fft(const typename Store<DT>::T *__restrict__ coef, const float *__restrict__ scales,
                 float2 *__restrict__ U, int H, int R, int b0, int p0, int np, ThrArgs thr,
                 const float2 *__restrict__ tw) {
-  constexpr int NT = Tile<N>::NT, M = Tile<N>::M, E = Tile<N>::E;
+  constexpr int NT = Tile<N, EM>::NT, M = Tile<N, EM>::M, E = Tile<N, EM>::E;
   __shared__ float2 lds[M * row_lds_len<N>()];
   const int t = threadIdx.x % NT, m = threadIdx.x / NT;
   const int row = blockIdx.x * M + m;
@@ -598,7 +614,7 @@ k_rows_coef_fft(const typename Store<DT>::T *__restrict__ coef, const float *__r
     if (!(fabsf(bb) >= db)) bb = 0.f;
     v[e] = make_float2(a, bb);
   }
-  fft_line<N, false>(v, t, LdsLine{lds + m * row_lds_len<N>(), 0}, tw);
+  row_fft<N, EM, false>(v, t, LdsLine{lds + m * row_lds_len<N>(), 0}, tw);
   if (ok) {
     float2 *Uo = U + ((size_t)bl * np + pp) * plane + (size_t)row * N;
 #pragma unroll
@@ -610,13 +626,13 @@ k_rows_coef_fft(const typename Store<DT>::T *__restrict__ coef, const float *__r
 // k_rows_coef_fft with the row-group loop and next-row prefetch (both
 // coefficient rows of the pair) of k_rows_thr, used for 16-bit storage
 // (32 x 512^2 FP16: step 2.24 -> 2.18 ms)
-template <int N, int DT>
-__global__ void __launch_bounds__(Tile<N>::THREADS / 2 > 0 ? Tile<N>::THREADS / 2 : 1)
+template <int N, int DT, int EM = 1>
+__global__ void __launch_bounds__((Tile<N, EM>::THREADS / 2 > 0 ? Tile<N, EM>::THREADS / 2 : 1))
 k_rows_coef_fft_pf(const typename Store<DT>::T *__restrict__ coef, const float *__restrict__ scales,
                    float2 *__restrict__ U, int H, int R, int b0, int p0, int np, ThrArgs thr,
                    const float2 *__restrict__ tw) {
-  constexpr int NT = Tile<N>::NT, E = Tile<N>::E;
-  constexpr int M = Tile<N>::M / 2 > 0 ? Tile<N>::M / 2 : 1;
+  constexpr int NT = Tile<N, EM>::NT, E = Tile<N, EM>::E;
+  constexpr int M = Tile<N, EM>::M / 2 > 0 ? Tile<N, EM>::M / 2 : 1;
   __shared__ float2 lds[M * row_lds_len<N>()];
   const int t = threadIdx.x % NT, m = threadIdx.x / NT;
   const int pp = blockIdx.y, bl = blockIdx.z, b = b0 + bl;
@@ -665,7 +681,7 @@ k_rows_coef_fft_pf(const typename Store<DT>::T *__restrict__ coef, const float *
       v[e] = make_float2(a, bb);
     }
     if (rg + G < nrg) load(rg + G);
-    fft_line<N, false>(v, t, LdsLine{lds + m * row_lds_len<N>(), 0}, tw);
+    row_fft<N, EM, false>(v, t, LdsLine{lds + m * row_lds_len<N>(), 0}, tw);
     const int row = rg * M + m;
     if (row < H) {
       float2 *Uo = Up + (size_t)row * N;
@@ -759,29 +775,34 @@ k_rows_thr(float2 *__restrict__ T, int H, int R, int b0, int p0, int np, float i
 // pair planes without the non-temporal hint (they stay in the Infinity
 // Cache).
 constexpr int kInvWide = 16, kInvNarrow = 8;
-template <int N, int MW>
+template <int N, int MW, int EM = 1>
 struct ITile {
-  using PL = Plan<N>;
+  using PL = Plan<N, EM>;
   static constexpr int NT = PL::NT;
   static constexpr int E = PL::E;
-  static constexpr int M = CTile<N>::M < MW ? CTile<N>::M : MW;
+  static constexpr int MC = EM == 1 ? CTile<N>::M : (NT * 16 <= 1024 ? 16 : 8);
+  static constexpr int M = MC < MW ? MC : MW;
   static constexpr int THREADS = M * NT;
 };
 
-template <int N, int BT, int MW>
-__global__ void __launch_bounds__((ITile<N, MW>::THREADS))
+template <int N, int BT, int MW, int EM = 1>
+__global__ void __launch_bounds__((ITile<N, MW, EM>::THREADS))
 k_cols_fft_acc(const float2 *__restrict__ U, const float *__restrict__ filt,
                const float *__restrict__ psi, float2 *__restrict__ ACC, float2 *__restrict__ part,
                int Btot, int W, int R, int b0, int nb, int p0, int np, int first, int last,
                const float2 *__restrict__ tw) {
-  constexpr int NT = ITile<N, MW>::NT, M = ITile<N, MW>::M, E = ITile<N, MW>::E;
-  using PL = typename ITile<N, MW>::PL;
+  constexpr int NT = ITile<N, MW, EM>::NT, M = ITile<N, MW, EM>::M, E = ITile<N, MW, EM>::E;
+  using PL = typename ITile<N, MW, EM>::PL;
   __shared__ float2 lds[M * N];
   const int m = threadIdx.x % M, t = threadIdx.x / M;
   const int col = col_tile() * M + m;
   const bool ok = col < W;
   const int cc = ok ? col : 0;
   const size_t plane = (size_t)N * W;
+  // element offsets within a plane from uniform plane bases: thread (m, t)
+  // owns rows t + e NT of column cc (32-bit offsets, so that the strided
+  // addresses are not held as 64-bit registers)
+  const unsigned o0 = (unsigned)t * W + cc, se = (unsigned)NT * W;
   // pair group z sums pairs [q0, q1) of the chunk into its own partial sum:
   // ACC for z = 0, part[z - 1] ([Btot] planes each) otherwise; with several
   // groups k_cols_acc_finish adds the partial sums after the last chunk.  A
@@ -793,29 +814,28 @@ k_cols_fft_acc(const float2 *__restrict__ U, const float *__restrict__ filt,
 #pragma unroll
   for (int bt = 0; bt < BT; ++bt) {
     const int bl = blockIdx.y * BT + bt;
-    const float2 *accp = dst + (size_t)(b0 + (bl < nb ? bl : 0)) * plane + cc;
+    const float2 *accp = dst + (size_t)(b0 + (bl < nb ? bl : 0)) * plane;
 #pragma unroll
     for (int e = 0; e < E; ++e)
-      acc[bt][e] = first ? make_float2(0.f, 0.f) : accp[(size_t)(t + e * NT) * W];
+      acc[bt][e] = first ? make_float2(0.f, 0.f) : accp[o0 + e * se];
   }
   for (int pp = q0; pp < q1; ++pp) {
     const int ia = 2 * (p0 + pp), ib = ia + 1;
-    const float *fa = filt + (size_t)ia * plane + cc;
-    const float *fb = filt + (size_t)(ib < R ? ib : ia) * plane + cc;
+    const float *fa = filt + (size_t)ia * plane;
+    const float *fb = filt + (size_t)(ib < R ? ib : ia) * plane;
     float a[E], bb[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const size_t o = (size_t)(t + e * NT) * W;
-      a[e] = fa[o];
-      bb[e] = ib < R ? fb[o] : 0.f;
+      a[e] = fa[o0 + e * se];
+      bb[e] = ib < R ? fb[o0 + e * se] : 0.f;
     }
 #pragma unroll
     for (int bt = 0; bt < BT; ++bt) {
       const int bl = blockIdx.y * BT + bt;
-      const float2 *Ui = U + ((size_t)(bl < nb ? bl : 0) * np + pp) * plane + cc;
+      const float2 *Ui = U + ((size_t)(bl < nb ? bl : 0) * np + pp) * plane;
       float2 v[E];
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = stream_load<SL_NT_STREAM && MW != kInvNarrow>(&Ui[(size_t)(t + e * NT) * W]);
+      for (int e = 0; e < E; ++e) v[e] = stream_load<SL_NT_STREAM && MW != kInvNarrow>(&Ui[o0 + e * se]);
       fft_line_p<PL, false>(v, t, LdsLine{lds + m, M}, tw);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -829,18 +849,17 @@ k_cols_fft_acc(const float2 *__restrict__ U, const float *__restrict__ filt,
   for (int bt = 0; bt < BT; ++bt) {
     const int bl = blockIdx.y * BT + bt;
     if (last) {
-      const float *ps = psi + cc;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const float d = ps[(size_t)(t + e * NT) * W];
+        const float d = psi[o0 + e * se];
         acc[bt][e] = make_float2(acc[bt][e].x / d, acc[bt][e].y / d);
       }
       fft_line_p<PL, true>(acc[bt], t, LdsLine{lds + m, M}, tw);
     }
     if (ok && bl < nb) {
-      float2 *accp = dst + (size_t)(b0 + bl) * plane + cc;
+      float2 *accp = dst + (size_t)(b0 + bl) * plane;
 #pragma unroll
-      for (int e = 0; e < E; ++e) accp[(size_t)(t + e * NT) * W] = acc[bt][e];
+      for (int e = 0; e < E; ++e) accp[o0 + e * se] = acc[bt][e];
     }
   }
 }
@@ -1244,13 +1263,22 @@ static int inv_bt(const Sys2D &s, int nb) {
   return nb >= 2 ? kInvBT : 1;
 }
 
+// columns per block of the inverse accumulation pass
+template <int N>
+static int inv_tile_m(const Sys2D &s, int nb) {
+  if constexpr (em2_length<N>()) {
+    if (s.line_em == 2) return ITile<N, kInvNarrow, 2>::M;
+  }
+  return nb == 1 ? ITile<N, kInvNarrow>::M : ITile<N, kInvWide>::M;
+}
+
 int inv_pair_groups(const Sys2D &s, int nb, int np) {
   if (SL_COL_V3_INV || !lines_supported(s.H)) return 1;
   int M = 0;
   switch (s.H) {
 #define X(N) \
   case N:    \
-    M = nb == 1 ? ITile<N, kInvNarrow>::M : ITile<N, kInvWide>::M; \
+    M = inv_tile_m<N>(s, nb); \
     break;
     SL_FOR_EACH_N(X)
 #undef X
@@ -1259,11 +1287,11 @@ int inv_pair_groups(const Sys2D &s, int nb, int np) {
   return pair_groups(s, ((s.W + M - 1) / M) * ((nb + bt - 1) / bt), np, 2, 16);
 }
 
-template <int N, int MW>
+template <int N, int MW, int EM = 1>
 static void launch_fwd3(const Sys2D &s, const float2 *F, float2 *T, Chunk c, hipStream_t st) {
-  using FT = FTile<N, MW>;
+  using FT = FTile<N, MW, EM>;
   const int tiles = (s.W + FT::M - 1) / FT::M, ny = (c.nb + kFwdBT - 1) / kFwdBT;
-  hipLaunchKernelGGL((k_cols_filter_ifft3<N, kFwdBT, MW>),
+  hipLaunchKernelGGL((k_cols_filter_ifft3<N, kFwdBT, MW, EM>),
                      dim3(tiles, ny, pair_groups(s, tiles * ny, c.np, 4, 32)), dim3(FT::THREADS),
                      0, st, F, s.filt, T, s.W, s.R, c.b0, c.nb, c.p0, c.np, s.twH);
 }
@@ -1290,26 +1318,42 @@ hipError_t launch_cols_filter_ifft(const Sys2D &s, const float2 *F, float2 *T, C
   return hipGetLastError();
 }
 
+template <int N, int DT, int EM>
+static void rows_coef_em(const Sys2D &s, const float2 *T, void *coef, const float *scales, Chunk c,
+                         float inv_hw, hipStream_t st) {
+  using CT = typename Store<DT>::T;
+  using TL = Tile<N, EM>;
+  if (DT != 0) {
+    constexpr int MP = TL::M / 2 > 0 ? TL::M / 2 : 1;
+    const int nrg = (s.H + MP - 1) / MP;
+    int G = nrg / 8 > 1 ? nrg / 8 : 1;
+    if ((long)G * c.np * c.nb < 8L * s.num_cu) G = nrg;
+    hipLaunchKernelGGL((k_rows_coef_pf<N, DT, EM>), dim3(G, c.np, c.nb), dim3(MP * TL::NT), 0, st, T,
+                       (CT *)coef, scales, s.H, s.R, c.b0, c.p0, c.np, inv_hw, s.twW);
+  } else {
+    hipLaunchKernelGGL((k_rows_coef<N, DT, EM>), dim3((s.H + TL::M - 1) / TL::M, c.np, c.nb),
+                       dim3(TL::THREADS), 0, st, T, (CT *)coef, scales, s.H, s.R, c.b0, c.p0, c.np,
+                       inv_hw, s.twW);
+  }
+}
+
+template <int N, int DT>
+static void rows_coef_n(const Sys2D &s, const float2 *T, void *coef, const float *scales, Chunk c,
+                        float inv_hw, hipStream_t st) {
+  if constexpr (em2_length<N>()) {
+    if (s.line_em == 2) return rows_coef_em<N, DT, 2>(s, T, coef, scales, c, inv_hw, st);
+  }
+  rows_coef_em<N, DT, 1>(s, T, coef, scales, c, inv_hw, st);
+}
+
 template <int DT>
 static hipError_t rows_coef_dt(const Sys2D &s, const float2 *T, void *coef, const float *scales,
                                Chunk c, hipStream_t st) {
-  using CT = typename Store<DT>::T;
   const float inv_hw = 1.0f / ((float)s.H * (float)s.W);
   switch (s.W) {
-#define X(N)                                                                                     \
-  case N:                                                                                        \
-    if (DT != 0) {                                                                               \
-      constexpr int MP = Tile<N>::M / 2 > 0 ? Tile<N>::M / 2 : 1;                                \
-      const int nrg = (s.H + MP - 1) / MP;                                                       \
-      int G = nrg / 8 > 1 ? nrg / 8 : 1;                                                         \
-      if ((long)G * c.np * c.nb < 8L * s.num_cu) G = nrg;                                        \
-      hipLaunchKernelGGL((k_rows_coef_pf<N, DT>), dim3(G, c.np, c.nb), dim3(MP * Tile<N>::NT), 0, \
-                         st, T, (CT *)coef, scales, s.H, s.R, c.b0, c.p0, c.np, inv_hw, s.twW);  \
-    } else {                                                                                     \
-      hipLaunchKernelGGL((k_rows_coef<N, DT>), row_grid<N>(s.H, c.np, c.nb),                     \
-                         dim3(Tile<N>::THREADS), 0, st, T, (CT *)coef, scales, s.H, s.R, c.b0,   \
-                         c.p0, c.np, inv_hw, s.twW);                                             \
-    }                                                                                            \
+#define X(N)                                                   \
+  case N:                                                      \
+    rows_coef_n<N, DT>(s, T, coef, scales, c, inv_hw, st);     \
     break;
     SL_FOR_EACH_N(X)
 #undef X
@@ -1344,26 +1388,41 @@ hipError_t launch_zero_u32(unsigned *p, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <int N, int DT, int EM>
+static void rows_coef_fft_em(const Sys2D &s, const void *coef, const float *scales, float2 *U,
+                             Chunk c, const ThrArgs &thr, hipStream_t st) {
+  using CT = typename Store<DT>::T;
+  using TL = Tile<N, EM>;
+  if (DT != 0) {
+    constexpr int MP = TL::M / 2 > 0 ? TL::M / 2 : 1;
+    const int nrg = (s.H + MP - 1) / MP;
+    int G = nrg / 8 > 1 ? nrg / 8 : 1;
+    if ((long)G * c.np * c.nb < 8L * s.num_cu) G = nrg;
+    hipLaunchKernelGGL((k_rows_coef_fft_pf<N, DT, EM>), dim3(G, c.np, c.nb), dim3(MP * TL::NT), 0,
+                       st, (const CT *)coef, scales, U, s.H, s.R, c.b0, c.p0, c.np, thr, s.twW);
+  } else {
+    hipLaunchKernelGGL((k_rows_coef_fft<N, DT, EM>), dim3((s.H + TL::M - 1) / TL::M, c.np, c.nb),
+                       dim3(TL::THREADS), 0, st, (const CT *)coef, scales, U, s.H, s.R, c.b0, c.p0,
+                       c.np, thr, s.twW);
+  }
+}
+
+template <int N, int DT>
+static void rows_coef_fft_n(const Sys2D &s, const void *coef, const float *scales, float2 *U,
+                            Chunk c, const ThrArgs &thr, hipStream_t st) {
+  if constexpr (em2_length<N>()) {
+    if (s.line_em == 2) return rows_coef_fft_em<N, DT, 2>(s, coef, scales, U, c, thr, st);
+  }
+  rows_coef_fft_em<N, DT, 1>(s, coef, scales, U, c, thr, st);
+}
+
 template <int DT>
 static hipError_t rows_coef_fft_dt(const Sys2D &s, const void *coef, const float *scales,
                                    float2 *U, Chunk c, const ThrArgs &thr, hipStream_t st) {
-  using CT = typename Store<DT>::T;
   switch (s.W) {
-#define X(N)                                                                                   \
-  case N:                                                                                      \
-    if (DT != 0) {                                                                             \
-      constexpr int MP = Tile<N>::M / 2 > 0 ? Tile<N>::M / 2 : 1;                              \
-      const int nrg = (s.H + MP - 1) / MP;                                                     \
-      int G = nrg / 8 > 1 ? nrg / 8 : 1;                                                       \
-      if ((long)G * c.np * c.nb < 8L * s.num_cu) G = nrg;                                      \
-      hipLaunchKernelGGL((k_rows_coef_fft_pf<N, DT>), dim3(G, c.np, c.nb),                     \
-                         dim3(MP * Tile<N>::NT), 0, st, (const CT *)coef, scales, U, s.H, s.R, \
-                         c.b0, c.p0, c.np, thr, s.twW);                                        \
-    } else {                                                                                   \
-      hipLaunchKernelGGL((k_rows_coef_fft<N, DT>), row_grid<N>(s.H, c.np, c.nb),               \
-                         dim3(Tile<N>::THREADS), 0, st, (const CT *)coef, scales, U, s.H, s.R, \
-                         c.b0, c.p0, c.np, thr, s.twW);                                        \
-    }                                                                                          \
+#define X(N)                                                     \
+  case N:                                                        \
+    rows_coef_fft_n<N, DT>(s, coef, scales, U, c, thr, st);      \
     break;
     SL_FOR_EACH_N(X)
 #undef X
@@ -1406,12 +1465,34 @@ hipError_t launch_rows_thr(const Sys2D &s, float2 *T, float inv_n, Chunk c, cons
   return hipGetLastError();
 }
 
+// With the EM = 2 line plan, 1024-point columns of the inverse accumulation
+// run 8 per block with 64 threads each (512 threads, 16 values per thread):
+// the EM = 1 instances (8 columns x 128 threads) spill registers at the
+// 128-VGPR cap of a 1024-thread block.  One image per block.
+template <int N>
+static bool cols_fft_acc_em2(const Sys2D &s, const float2 *U, float2 *ACC, float2 *part, int G,
+                             int Btot, Chunk c, bool first, bool last, hipStream_t st) {
+  if constexpr (em2_length<N>()) {
+    if (s.line_em == 2 && !SL_COL_V3_INV) {
+      using IT = ITile<N, kInvNarrow, 2>;
+      hipLaunchKernelGGL((k_cols_fft_acc<N, 1, kInvNarrow, 2>),
+                         dim3((s.W + IT::M - 1) / IT::M, c.nb, G), dim3(IT::THREADS), 0, st, U,
+                         s.filt, s.psi, ACC, part, Btot, s.W, s.R, c.b0, c.nb, c.p0, c.np,
+                         (int)first, (int)(last && G == 1), s.twH);
+      return true;
+    }
+  }
+  return false;
+}
+
 hipError_t launch_cols_fft_acc(const Sys2D &s, const float2 *U, float2 *ACC, float2 *part,
                                int G, int Btot, Chunk c, bool first, bool last, hipStream_t st) {
   if (G < 1 || (G > 1 && (!part || SL_COL_V3_INV))) return hipErrorInvalidValue;
   switch (s.H) {
 #define X(N)                                                                                    \
   case N:                                                                                       \
+    if (cols_fft_acc_em2<N>(s, U, ACC, part, G, Btot, c, first, last, st))                     \
+      break;                                                                                    \
     if (SL_COL_V3_INV)                                                                          \
       hipLaunchKernelGGL((k_cols_fft_acc3<N, kInvBT>), col_grid<N>(s.W, (c.nb + kInvBT - 1) / kInvBT), \
                          dim3(CTile<N>::THREADS), 0, st, U, s.filt, s.psi, ACC, s.W, s.R, c.b0, \

@@ -7,8 +7,10 @@
 // which trades launch count against Infinity Cache residency of the
 // intermediate) and, in 2D, the column tile shape of the inverse
 // accumulation (one or two images per block) and whether small grids split
-// the subband-pair loop over blocks.  Results are cached in a small text
-// file, one line per class: key, chunk bytes, images per block, split.
+// the subband-pair loop over blocks, and for classes with 1024-point lines
+// the line plan (values per thread of those lines' FFTs, kernels2d.hip).
+// Results are cached in a small text file, one line per class: key, chunk
+// bytes, images per block, split, line plan.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -85,7 +87,7 @@ std::string tune_key(const sl_system *s, int count) {
 
 struct Sched {
   size_t chunk;
-  int inv_images, split;
+  int inv_images, split, line_em;
 };
 
 std::map<std::string, Sched> load_cache(const char *path) {
@@ -96,9 +98,10 @@ std::map<std::string, Sched> load_cache(const char *path) {
   while (std::getline(f, line)) {
     std::istringstream ls(line);
     std::string key;
-    Sched v{0, 0, 1};
+    Sched v{0, 0, 1, 1};
     if (!(ls >> key >> v.chunk)) continue;
     if (!(ls >> v.inv_images >> v.split)) v.inv_images = 0, v.split = 1;
+    if (!(ls >> v.line_em) || (v.line_em != 1 && v.line_em != 2)) v.line_em = 1;
     c[key] = v;
   }
   return c;
@@ -109,16 +112,24 @@ void save_cache(const char *path, const std::map<std::string, Sched> &c) {
   std::ofstream f(path);
   for (auto &kv : c)
     f << kv.first << " " << kv.second.chunk << " " << kv.second.inv_images << " "
-      << kv.second.split << "\n";
+      << kv.second.split << " " << kv.second.line_em << "\n";
 }
 
 void apply(sl_system *s, const Sched &v) {
   s->chunk_cap = v.chunk;
   s->inv_images = v.inv_images;
   s->split_pairs = v.split;
+  s->line_em = v.line_em;
 }
 
-Sched current(const sl_system *s) { return {s->chunk_cap, s->inv_images, s->split_pairs}; }
+Sched current(const sl_system *s) {
+  return {s->chunk_cap, s->inv_images, s->split_pairs, s->line_em};
+}
+
+// a class has a second line plan to try when it has 1024-point lines
+bool has_em2(const sl_system *s) {
+  return s->cfg.ndim == 2 && (s->cfg.dims[0] == 1024 || s->cfg.dims[1] == 1024);
+}
 
 #define CK(expr)                                            \
   do {                                                      \
@@ -234,13 +245,15 @@ int sl_multi_autotune(sl_multi *m, const float *const *x_dev, void *const *coeff
     }
     float best = 1e30f;
     Sched best_s = current(sy);
-    // the block shape only applies to 2D systems
+    // the block shape only applies to 2D systems, the line plan to 1024-point lines
     const int n_images = sy->cfg.ndim == 2 ? 2 : 1, n_split = sy->cfg.ndim == 2 ? 2 : 1;
+    const int n_em = has_em2(sy) ? 2 : 1;
     for (size_t mb : cand_mb)
       for (int ii = 0; ii < n_images && rc == SL_OK; ++ii)
-        for (int si = 0; si < n_split && rc == SL_OK; ++si) {
+        for (int si = 0; si < n_split && rc == SL_OK; ++si)
+        for (int em = 1; em <= n_em && rc == SL_OK; ++em) {
           const Sched cand{mb << 20, sy->cfg.ndim == 2 ? cand_images[ii] : sy->inv_images,
-                           sy->cfg.ndim == 2 ? cand_split[si] : sy->split_pairs};
+                           sy->cfg.ndim == 2 ? cand_split[si] : sy->split_pairs, em};
           apply(sy, cand);
           size_t need = 0;
           sl_workspace_size(sy, m->counts[s], &need);

@@ -22,6 +22,7 @@ struct sl_system {
   size_t chunk_cap = 0;
   int inv_images = 0;             // images per inverse accumulation block (0 = auto)
   int split_pairs = 1;            // small grids split the pair loop over blocks
+  int line_em = 1;                // line plan of 1024-point lines (1 or 2)
   bool plane3d = true;            // volumes: y and x passes of a z-slice in LDS
   bool wavelet = false;           // built by sl_build_wavelet_system
   int xcd = 0;                    // 2D: XCD-cooperative passes where supported

@@ -171,3 +171,35 @@ def test_c4_uneven_64_images():
               flush=True)
         worst = max(worst, max(max(e) for e in errs))
     print(f"worst relL2 over the 64 images: {worst:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_line_plan_1024(dtype):
+    # the second line plan of 1024-point lines (one wavefront per row, 512-thread
+    # inverse accumulation blocks) against the default plan and the oracle
+    print(f"case: 1024^2 line plans, B=2, J=2, {dtype}", flush=True)
+    dims = (1024, 1024)
+    s = B.System(dims, 2, [1, 1], dtype=dtype)
+    xs = np.stack([syn.noisy_cartoon2d(*dims, 4200 + b, 0.1)[1] for b in range(2)])
+    xg = torch.from_numpy(xs.astype(np.float32)).to(DEV)
+    sg = torch.tensor([0.1, 0.1], dtype=torch.float32, device=DEV)
+    K = [3.0, 4.0]
+    outs = {}
+    for em in (1, 2):
+        s.set_line_plan(em)
+        assert s.line_plan() == em
+        c, sc = s.forward(xg)
+        r = s.inverse(c, sc)
+        d = s.inverse(c, sc, sigma=sg, K=K)
+        torch.cuda.synchronize()
+        outs[em] = (c.float().cpu().numpy() * (sc.cpu().numpy()[:, :, None, None]
+                                               if dtype != "f32" else 1.0),
+                    r.cpu().numpy(), d.cpu().numpy())
+    s.set_line_plan(1)
+    tol_gpu = 1e-6 if dtype == "f32" else 1e-3
+    for k in range(3):
+        assert rel(outs[2][k], outs[1][k]) < tol_gpu, k
+    tol = 1e-5 if dtype == "f32" else 2e-3
+    o = S.build_2d(dims, 2, [1, 1])
+    assert rel(outs[2][0][0], T.forward(xs[0], o.filters)) < tol
+    assert rel(outs[2][1], xs) < tol
