@@ -364,8 +364,20 @@ int sl_multi_run(sl_multi *m, int what, const float *const *x_dev, void *const *
 int sl_multi_autotune(sl_multi *m, const float *const *x_dev, void *const *coeffs_dev,
                       float *const *scales_dev, float *const *out_dev, void *workspace_dev,
                       size_t workspace_bytes, const char *cache_path, void *stream);
-/* Captures one run (same arguments as sl_multi_run) into a HIP graph with
- * one branch per class; sl_multi_graph_launch replays it on a stream.  The
+/* Schedule of a multi-batch: per_class = 0 (default) runs, where every class
+ * supports it (2D, one storage type, row lengths with a wavefront-local line
+ * plan; 1024-point classes need line plan 2), the multi-class schedule: each
+ * class's spectrum and column passes, and for every step one coefficient
+ * row launch whose flat work list holds the row blocks of all classes
+ * (largest class first); otherwise, or with per_class = 1, each class runs
+ * its own passes (as separate graph branches in sl_multi_graph_build).
+ * sl_multi_autotune times both and keeps the faster.  sl_multi_schedule
+ * reports whether the multi-class schedule is in use.                      */
+int sl_multi_set_schedule(sl_multi *m, int per_class);
+int sl_multi_schedule(sl_multi *m, int *multi_class_rows);
+/* Captures one run (same arguments as sl_multi_run) into a HIP graph (one
+ * branch per class in the per-class schedule, one sequence in the
+ * multi-class schedule); sl_multi_graph_launch replays it on a stream.  The
  * buffers are baked into the graph.  Per-pass timing must be off.          */
 int sl_multi_graph_build(sl_multi *m, int what, const float *const *x_dev,
                          void *const *coeffs_dev, float *const *scales_dev,

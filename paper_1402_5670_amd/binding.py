@@ -143,6 +143,8 @@ _SIGS = {
     "sl_multi_graph_build": ([ctypes.c_void_p, ctypes.c_int] + [ctypes.c_void_p] * 6 +
                              [ctypes.c_void_p, ctypes.c_size_t], ctypes.c_int),
     "sl_multi_graph_launch": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "sl_multi_set_schedule": ([ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
+    "sl_multi_schedule": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "sl_timing_enable": ([ctypes.c_int], ctypes.c_int),
     "sl_timing_reset": ([], ctypes.c_int),
     "sl_timing_num_passes": ([], ctypes.c_int),
@@ -666,6 +668,14 @@ class Multi:
         a = self._args(xs, coeffs, scales, sigmas, K, outs)
         check(lib().sl_multi_graph_build(self._h, int(what), *a, _ptr(workspace),
                                          workspace.numel()))
+
+    def set_schedule(self, per_class):
+        check(lib().sl_multi_set_schedule(self._h, int(bool(per_class))))
+
+    def multi_class_rows(self):
+        v = ctypes.c_int()
+        check(lib().sl_multi_schedule(self._h, ctypes.byref(v)))
+        return bool(v.value)
 
     def graph_launch(self):
         check(lib().sl_multi_graph_launch(self._h, _stream()))

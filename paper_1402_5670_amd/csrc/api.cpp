@@ -522,6 +522,123 @@ uint64_t bits_of(double v) {
 
 }  // namespace
 
+bool sl::multi2d_supported(const MultiClass2D *cls, int n) {
+  if (n < 1 || n > kMaxMultiClasses) return false;
+  for (int i = 0; i < n; ++i) {
+    const sl_system *s = cls[i].s;
+    if (!s || s->cfg.ndim != 2 || s->cfg.dtype != cls[0].s->cfg.dtype) return false;
+    if (!sl::multi_rows_supported(view2d(s))) return false;
+  }
+  return true;
+}
+
+int sl::run_multi2d(const MultiClass2D *cls, int n, int what, const float *K, hipStream_t st) {
+  if (!multi2d_supported(cls, n)) return fail(SL_EUNSUPPORTED, "classes not supported by run_multi2d");
+  std::vector<std::vector<sl::Chunk>> chunks(n);
+  size_t steps = 0;
+  for (int i = 0; i < n; ++i) {
+    const MultiClass2D &c = cls[i];
+    int rc = check_call(c.s, c.B, c.x ? (const void *)c.x : c.coef, c.coef, c.ws, c.ws_bytes);
+    if (rc) return rc;
+    int nb, np;
+    chunk_plan(c.s, c.B, nb, np);
+    const int P = (c.s->R + 1) / 2;
+    for (int b0 = 0; b0 < c.B; b0 += nb)
+      for (int p0 = 0; p0 < P; p0 += np)
+        chunks[i].push_back({b0, std::min(nb, c.B - b0), p0, std::min(np, P - p0)});
+    steps = std::max(steps, chunks[i].size());
+  }
+  const int dtype = cls[0].s->cfg.dtype;
+  if (what & 1) {
+    // per class: row DFT of the images, column DFT, storage scales
+    for (int i = 0; i < n; ++i) {
+      const MultiClass2D &c = cls[i];
+      const Layout L = layout(c.s, c.B);
+      char *ws = (char *)c.ws;
+      float2 *F = (float2 *)(ws + L.off_F);
+      unsigned *xmax = (unsigned *)(ws + L.off_xmax);
+      const sl::Sys2D v = view2d(c.s);
+      const bool scaled = dtype != SL_F32;
+      if (scaled && !c.scales) return fail(SL_EINVAL, "scales are required for F16/BF16 storage");
+      if (scaled) SL_LAUNCH(P_AUX, st, sl::launch_zero_u32(xmax, c.B, st));
+      SL_LAUNCH(P_ROWS_REAL_FFT, st,
+                sl::launch_rows_real_fft(v, c.x, F, scaled ? xmax : nullptr, c.B, st));
+      SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(v, F, F, c.B, false, st));
+      if (scaled) SL_LAUNCH(P_AUX, st, sl::launch_scales(v, xmax, c.scales, c.B, st));
+    }
+    for (size_t k = 0; k < steps; ++k) {
+      sl::MultiRows mr{};
+      for (int i = 0; i < n; ++i) {
+        if (k >= chunks[i].size()) continue;
+        const MultiClass2D &c = cls[i];
+        const Layout L = layout(c.s, c.B);
+        char *ws = (char *)c.ws;
+        const sl::Sys2D v = view2d(c.s);
+        float2 *F = (float2 *)(ws + L.off_F), *T = (float2 *)(ws + L.off_chunk);
+        SL_LAUNCH(P_COLS_FILTER_IFFT, st, sl::launch_cols_filter_ifft(v, F, T, chunks[i][k], st));
+        sl::MultiRowClass &mc = mr.c[mr.n++];
+        sl::multi_rows_class_geometry(v, chunks[i][k], mc);
+        mc.T = T;
+        mc.coef = c.coef;
+        mc.scales = c.scales;
+      }
+      SL_LAUNCH(P_ROWS_COEF, st, sl::launch_rows_multi(mr, dtype, true, st));
+    }
+  }
+  if (what & 2) {
+    std::vector<int> groups(n);
+    for (int i = 0; i < n; ++i) groups[i] = inv_groups(cls[i].s, cls[i].B);
+    for (size_t k = 0; k < steps; ++k) {
+      sl::MultiRows mr{};
+      for (int i = 0; i < n; ++i) {
+        if (k >= chunks[i].size()) continue;
+        const MultiClass2D &c = cls[i];
+        const Layout L = layout(c.s, c.B);
+        const sl::Sys2D v = view2d(c.s);
+        sl::MultiRowClass &mc = mr.c[mr.n++];
+        sl::multi_rows_class_geometry(v, chunks[i][k], mc);
+        mc.U = (float2 *)((char *)c.ws + L.off_chunk);
+        mc.coef = c.coef;
+        mc.scales = c.scales;
+        mc.thr.sigma = c.sigma;
+        mc.thr.l2 = c.s->d_l2;
+        mc.thr.jof = c.s->d_jof;
+        if (c.sigma) {
+          if (!K) return fail(SL_EINVAL, "K is required with sigma");
+          if (c.s->cfg.J > sl::kMaxScales) return fail(SL_EUNSUPPORTED, "too many scales");
+          for (int j = 0; j < c.s->cfg.J; ++j) mc.thr.K[j] = K[j];
+        }
+      }
+      SL_LAUNCH(P_ROWS_COEF_FFT, st, sl::launch_rows_multi(mr, dtype, false, st));
+      for (int i = 0; i < n; ++i) {
+        if (k >= chunks[i].size()) continue;
+        const MultiClass2D &c = cls[i];
+        const Layout L = layout(c.s, c.B);
+        char *ws = (char *)c.ws;
+        const sl::Sys2D v = view2d(c.s);
+        const sl::Chunk &ch = chunks[i][k];
+        const int P = (c.s->R + 1) / 2;
+        SL_LAUNCH(P_COLS_FFT_ACC, st,
+                  sl::launch_cols_fft_acc(v, (float2 *)(ws + L.off_chunk), (float2 *)(ws + L.off_F),
+                                          (float2 *)(ws + L.off_part), groups[i], c.B, ch,
+                                          ch.p0 == 0, ch.p0 + ch.np == P, st));
+      }
+    }
+    for (int i = 0; i < n; ++i) {
+      const MultiClass2D &c = cls[i];
+      const Layout L = layout(c.s, c.B);
+      char *ws = (char *)c.ws;
+      const sl::Sys2D v = view2d(c.s);
+      float2 *ACC = (float2 *)(ws + L.off_F);
+      if (groups[i] > 1)
+        SL_LAUNCH(P_COLS_FFT_ACC, st,
+                  sl::launch_cols_acc_finish(v, ACC, (float2 *)(ws + L.off_part), groups[i], c.B, st));
+      SL_LAUNCH(P_ROWS_REAL_IFFT, st, sl::launch_rows_real_ifft(v, ACC, c.out, c.B, st));
+    }
+  }
+  return SL_OK;
+}
+
 int sl::set_error(int code, const std::string &msg) { return fail(code, msg); }
 bool sl::set_capturing(bool on) {
   const bool was = g_capturing;

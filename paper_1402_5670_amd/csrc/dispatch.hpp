@@ -98,6 +98,31 @@ hipError_t launch_cols_acc_finish(const Sys2D &s, float2 *ACC, const float2 *par
 // ACC -> x (row inverse DFT, real part, 1/(HW))
 hipError_t launch_rows_real_ifft(const Sys2D &s, const float2 *V, float *x, int B, hipStream_t st);
 
+// ---- multi-class coefficient row passes (uneven batches) ---------------------
+// One launch runs the coefficient row pass of several size classes: the
+// forward's row IDFT and coefficient store (T -> coef, as launch_rows_coef)
+// or the inverse's coefficient load, threshold and row DFT (coef -> U, as
+// launch_rows_coef_fft).  Every class must have the same storage type.
+constexpr int kMaxMultiClasses = 8;
+struct MultiRowClass {
+  const float2 *T;        // forward input (chunk pair planes)
+  float2 *U;              // inverse output (chunk pair planes)
+  void *coef;
+  const float *scales;
+  const float2 *tw;       // twiddles of the row length
+  ThrArgs thr;            // inverse threshold
+  float inv_hw;
+  int W, H, R, b0, p0, np, G, nblocks, block0;
+};
+struct MultiRows {
+  MultiRowClass c[kMaxMultiClasses];
+  int n;
+};
+bool multi_rows_supported(const Sys2D &s);
+// fills the geometry fields of k for chunk c of the class with view s
+void multi_rows_class_geometry(const Sys2D &s, const Chunk &c, MultiRowClass &k);
+hipError_t launch_rows_multi(MultiRows &a, int dtype, bool forward, hipStream_t st);
+
 // ---- XCD-cooperative passes (xcd2d.hip) --------------------------------------
 // 512 x 512 planes, float32 coefficients: the 32 workgroups of each XCD
 // transform one image at a time and exchange every plane through a scratch

@@ -488,16 +488,19 @@ k_rows_coef(const float2 *__restrict__ T, typename Store<DT>::T *__restrict__ co
 // k_rows_coef with the row-group loop and next-row prefetch of k_rows_thr,
 // used for 16-bit storage, whose stores are half as long (32 x 512^2 FP16:
 // step 2.29 -> 2.21 ms; with FP32 coefficients it was 4% slower)
-template <int N, int DT, int EM = 1>
-__global__ void __launch_bounds__((Tile<N, EM>::THREADS / 2 > 0 ? Tile<N, EM>::THREADS / 2 : 1))
-k_rows_coef_pf(const float2 *__restrict__ T, typename Store<DT>::T *__restrict__ coef,
-               const float *__restrict__ scales, int H, int R, int b0, int p0, int np,
-               float inv_hw, const float2 *__restrict__ tw) {
+// Body of the prefetching coefficient row pass for one block: M lines of NT
+// threads, row groups gx, gx + G, ... of pair pp of chunk image bl.  Shared
+// by k_rows_coef_pf (grid = (G, np, nb)) and the multi-class row pass.
+template <int N, int DT, int EM, int M>
+__device__ __forceinline__ void rows_coef_pf_body(float2 *lds, const float2 *__restrict__ T,
+                                                  typename Store<DT>::T *__restrict__ coef,
+                                                  const float *__restrict__ scales, int H, int R,
+                                                  int b0, int p0, int np, float inv_hw,
+                                                  const float2 *__restrict__ tw, int gx, int G,
+                                                  int pp, int bl) {
   constexpr int NT = Tile<N, EM>::NT, E = Tile<N, EM>::E;
-  constexpr int M = Tile<N, EM>::M / 2 > 0 ? Tile<N, EM>::M / 2 : 1;
-  __shared__ float2 lds[M * row_lds_len<N>()];
   const int t = threadIdx.x % NT, m = threadIdx.x / NT;
-  const int pp = blockIdx.y, bl = blockIdx.z, b = b0 + bl;
+  const int b = b0 + bl;
   const int ia = 2 * (p0 + pp), ib = ia + 1;
   const size_t plane = (size_t)H * N;
   const float2 *Tp = T + ((size_t)bl * np + pp) * plane;
@@ -509,7 +512,7 @@ k_rows_coef_pf(const float2 *__restrict__ T, typename Store<DT>::T *__restrict__
   using Raw = typename Store<DT>::Raw;
   Raw *ca0 = (Raw *)(coef + ((size_t)b * R + ia) * plane);
   Raw *cb0 = (Raw *)(coef + ((size_t)b * R + (ib < R ? ib : ia)) * plane);
-  const int nrg = (H + M - 1) / M, G = (int)gridDim.x;
+  const int nrg = (H + M - 1) / M;
   float2 nx[E];
   auto load = [&](int rg) {
     const int row = rg * M + m;
@@ -517,8 +520,8 @@ k_rows_coef_pf(const float2 *__restrict__ T, typename Store<DT>::T *__restrict__
 #pragma unroll
     for (int e = 0; e < E; ++e) nx[e] = src[t + e * NT];
   };
-  if ((int)blockIdx.x < nrg) load(blockIdx.x);
-  for (int rg = blockIdx.x; rg < nrg; rg += G) {
+  if (gx < nrg) load(gx);
+  for (int rg = gx; rg < nrg; rg += G) {
     float2 v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = nx[e];
@@ -536,6 +539,18 @@ k_rows_coef_pf(const float2 *__restrict__ T, typename Store<DT>::T *__restrict__
       }
     }
   }
+}
+
+template <int N, int DT, int EM = 1>
+__global__ void __launch_bounds__((Tile<N, EM>::THREADS / 2 > 0 ? Tile<N, EM>::THREADS / 2 : 1))
+k_rows_coef_pf(const float2 *__restrict__ T, typename Store<DT>::T *__restrict__ coef,
+               const float *__restrict__ scales, int H, int R, int b0, int p0, int np,
+               float inv_hw, const float2 *__restrict__ tw) {
+  constexpr int M = Tile<N, EM>::M / 2 > 0 ? Tile<N, EM>::M / 2 : 1;
+  __shared__ float2 lds[M * row_lds_len<N>()];
+  rows_coef_pf_body<N, DT, EM, M>(lds, T, coef, scales, H, R, b0, p0, np, inv_hw, tw,
+                                  (int)blockIdx.x, (int)gridDim.x, (int)blockIdx.y,
+                                  (int)blockIdx.z);
 }
 
 // scale_{b,i} = 2^(ceil(log2(max|x_b| * ||psi_i||_1)) - 15): |c| <= max|x| ||psi||_1
@@ -626,16 +641,16 @@ k_rows_coef_fft(const typename Store<DT>::T *__restrict__ coef, const float *__r
 // k_rows_coef_fft with the row-group loop and next-row prefetch (both
 // coefficient rows of the pair) of k_rows_thr, used for 16-bit storage
 // (32 x 512^2 FP16: step 2.24 -> 2.18 ms)
-template <int N, int DT, int EM = 1>
-__global__ void __launch_bounds__((Tile<N, EM>::THREADS / 2 > 0 ? Tile<N, EM>::THREADS / 2 : 1))
-k_rows_coef_fft_pf(const typename Store<DT>::T *__restrict__ coef, const float *__restrict__ scales,
-                   float2 *__restrict__ U, int H, int R, int b0, int p0, int np, ThrArgs thr,
-                   const float2 *__restrict__ tw) {
+// Body of the prefetching inverse coefficient row pass for one block (as
+// rows_coef_pf_body): shared by k_rows_coef_fft_pf and the multi-class pass.
+template <int N, int DT, int EM, int M>
+__device__ __forceinline__ void rows_coef_fft_pf_body(
+    float2 *lds, const typename Store<DT>::T *__restrict__ coef, const float *__restrict__ scales,
+    float2 *__restrict__ U, int H, int R, int b0, int p0, int np, const ThrArgs &thr,
+    const float2 *__restrict__ tw, int gx, int G, int pp, int bl) {
   constexpr int NT = Tile<N, EM>::NT, E = Tile<N, EM>::E;
-  constexpr int M = Tile<N, EM>::M / 2 > 0 ? Tile<N, EM>::M / 2 : 1;
-  __shared__ float2 lds[M * row_lds_len<N>()];
   const int t = threadIdx.x % NT, m = threadIdx.x / NT;
-  const int pp = blockIdx.y, bl = blockIdx.z, b = b0 + bl;
+  const int b = b0 + bl;
   const int ia = 2 * (p0 + pp), ib = ia + 1;
   const bool has_b = ib < R;
   const size_t plane = (size_t)H * N;
@@ -658,7 +673,7 @@ k_rows_coef_fft_pf(const typename Store<DT>::T *__restrict__ coef, const float *
   const Raw *ca0 = (const Raw *)(coef + ((size_t)b * R + ia) * plane);
   const Raw *cb0 = (const Raw *)(coef + ((size_t)b * R + (has_b ? ib : ia)) * plane);
   float2 *Up = U + ((size_t)bl * np + pp) * plane;
-  const int nrg = (H + M - 1) / M, G = (int)gridDim.x;
+  const int nrg = (H + M - 1) / M;
   Raw na[E], nb_[E];
   auto load = [&](int rg) {
     const int row = rg * M + m;
@@ -669,8 +684,8 @@ k_rows_coef_fft_pf(const typename Store<DT>::T *__restrict__ coef, const float *
       nb_[e] = coef_load(cb0 + o + t + e * NT);   // a valid plane; ignored without a partner
     }
   };
-  if ((int)blockIdx.x < nrg) load(blockIdx.x);
-  for (int rg = blockIdx.x; rg < nrg; rg += G) {
+  if (gx < nrg) load(gx);
+  for (int rg = gx; rg < nrg; rg += G) {
     float2 v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -689,6 +704,135 @@ k_rows_coef_fft_pf(const typename Store<DT>::T *__restrict__ coef, const float *
       for (int e = 0; e < E; ++e) Uo[t + e * NT] = v[e];
     }
   }
+}
+
+template <int N, int DT, int EM = 1>
+__global__ void __launch_bounds__((Tile<N, EM>::THREADS / 2 > 0 ? Tile<N, EM>::THREADS / 2 : 1))
+k_rows_coef_fft_pf(const typename Store<DT>::T *__restrict__ coef, const float *__restrict__ scales,
+                   float2 *__restrict__ U, int H, int R, int b0, int p0, int np, ThrArgs thr,
+                   const float2 *__restrict__ tw) {
+  constexpr int M = Tile<N, EM>::M / 2 > 0 ? Tile<N, EM>::M / 2 : 1;
+  __shared__ float2 lds[M * row_lds_len<N>()];
+  rows_coef_fft_pf_body<N, DT, EM, M>(lds, coef, scales, U, H, R, b0, p0, np, thr, tw,
+                                      (int)blockIdx.x, (int)gridDim.x, (int)blockIdx.y,
+                                      (int)blockIdx.z);
+}
+
+
+// ---------------------------------------------------------------------------
+// Multi-class coefficient row passes (uneven batches): one launch covers the
+// row blocks of every size class of a schedule step.  The flat block index
+// is the work list: class c owns blocks [block0_c, block0_c+1), listed
+// largest class first, and a block of class c decodes (row group, pair,
+// image) from its local index as the single-class launch's grid would.  A
+// block has 512 threads; a class of line length N runs 512 / NT lines per
+// block with the wavefront-local line FFT of its plan (1024-point lines use
+// the 16-values-per-thread plan), and the dynamic LDS holds the largest
+// class's rows.
+// ---------------------------------------------------------------------------
+constexpr int kMultiThreads = 512;
+
+template <int N, int DT, int EM, bool FWD>
+__device__ __forceinline__ void multi_row_class(const MultiRowClass &k, float2 *lds, int gx,
+                                                int pp, int bl) {
+  constexpr int M = kMultiThreads / Plan<N, EM>::NT;
+  using CT = typename Store<DT>::T;
+  if constexpr (FWD)
+    rows_coef_pf_body<N, DT, EM, M>(lds, k.T, (CT *)k.coef, k.scales, k.H, k.R, k.b0, k.p0, k.np,
+                                    k.inv_hw, k.tw, gx, k.G, pp, bl);
+  else
+    rows_coef_fft_pf_body<N, DT, EM, M>(lds, (const CT *)k.coef, k.scales, k.U, k.H, k.R, k.b0,
+                                        k.p0, k.np, k.thr, k.tw, gx, k.G, pp, bl);
+}
+
+#define SL_MULTI_ROW_LENGTHS(X) X(64, 1) X(96, 1) X(128, 1) X(192, 1) X(256, 1) X(384, 1) \
+  X(512, 1) X(768, 1) X(1024, 2)
+
+template <int DT, bool FWD>
+__global__ void __launch_bounds__(kMultiThreads) k_rows_multi(MultiRows a) {
+  extern __shared__ float2 mlds[];
+  int c = 0;
+  while (c + 1 < a.n && (int)blockIdx.x >= a.c[c + 1].block0) ++c;
+  const MultiRowClass &k = a.c[c];
+  const int local = (int)blockIdx.x - k.block0;
+  const int gx = local % k.G, pp = (local / k.G) % k.np, bl = local / (k.G * k.np);
+  switch (k.W) {
+#define X(N, EM)                                                   \
+  case N:                                                          \
+    multi_row_class<N, DT, EM, FWD>(k, mlds, gx, pp, bl);          \
+    break;
+    SL_MULTI_ROW_LENGTHS(X)
+#undef X
+  }
+}
+
+// lines per block and LDS bytes of a class in the multi-class row pass (0 if
+// its length has no wavefront-local plan here)
+static int multi_row_lines(int W, size_t *lds_bytes) {
+  switch (W) {
+#define X(N, EM)                                                                           \
+  case N:                                                                                  \
+    if (lds_bytes)                                                                         \
+      *lds_bytes = (size_t)(kMultiThreads / Plan<N, EM>::NT) * row_lds_len<N>() * sizeof(float2); \
+    return kMultiThreads / Plan<N, EM>::NT;
+    SL_MULTI_ROW_LENGTHS(X)
+#undef X
+    default:
+      return 0;
+  }
+}
+
+bool multi_rows_supported(const Sys2D &s) {
+  return multi_row_lines(s.W, nullptr) > 0 && (s.W != 1024 || s.line_em == 2);
+}
+
+void multi_rows_class_geometry(const Sys2D &s, const Chunk &c, MultiRowClass &k) {
+  const int M = multi_row_lines(s.W, nullptr);
+  const int nrg = (s.H + M - 1) / M;
+  int G = nrg / 8 > 1 ? nrg / 8 : 1;
+  if ((long)G * c.np * c.nb < 8L * s.num_cu) G = nrg;
+  k.W = s.W;
+  k.H = s.H;
+  k.R = s.R;
+  k.b0 = c.b0;
+  k.p0 = c.p0;
+  k.np = c.np;
+  k.G = G;
+  k.nblocks = G * c.np * c.nb;
+  k.tw = s.twW;
+  k.inv_hw = 1.0f / ((float)s.H * (float)s.W);
+}
+
+hipError_t launch_rows_multi(MultiRows &a, int dtype, bool forward, hipStream_t st) {
+  if (a.n < 1 || a.n > kMaxMultiClasses) return hipErrorInvalidValue;
+  // largest classes first: their blocks are dispatched first
+  for (int i = 1; i < a.n; ++i)
+    for (int j = i; j > 0 && (long)a.c[j].nblocks * a.c[j].W > (long)a.c[j - 1].nblocks * a.c[j - 1].W; --j) {
+      const MultiRowClass t = a.c[j];
+      a.c[j] = a.c[j - 1];
+      a.c[j - 1] = t;
+    }
+  size_t lds = 0;
+  int total = 0;
+  for (int i = 0; i < a.n; ++i) {
+    size_t b = 0;
+    if (multi_row_lines(a.c[i].W, &b) == 0) return hipErrorInvalidValue;
+    lds = b > lds ? b : lds;
+    a.c[i].block0 = total;
+    total += a.c[i].nblocks;
+  }
+  if (total < 1) return hipSuccess;
+  const dim3 grid(total), block(kMultiThreads);
+  if (forward) {
+    if (dtype == 1) hipLaunchKernelGGL((k_rows_multi<1, true>), grid, block, lds, st, a);
+    else if (dtype == 2) hipLaunchKernelGGL((k_rows_multi<2, true>), grid, block, lds, st, a);
+    else hipLaunchKernelGGL((k_rows_multi<0, true>), grid, block, lds, st, a);
+  } else {
+    if (dtype == 1) hipLaunchKernelGGL((k_rows_multi<1, false>), grid, block, lds, st, a);
+    else if (dtype == 2) hipLaunchKernelGGL((k_rows_multi<2, false>), grid, block, lds, st, a);
+    else hipLaunchKernelGGL((k_rows_multi<0, false>), grid, block, lds, st, a);
+  }
+  return hipGetLastError();
 }
 
 // Denoising without materialised coefficients: the forward transform's last

@@ -1,7 +1,10 @@
 // Uneven batches: images of several sizes in one schedule (declared in
 // include/shearlet.h).  Each size class runs the batched passes of its own
-// system; the classes are independent, so a captured HIP graph forks one
-// branch per class and the GPU runs the branches concurrently.  An autotuner
+// system.  Two schedules: per class (the classes are independent, so a
+// captured HIP graph forks one branch per class and the GPU runs the
+// branches concurrently), or multi-class (one stream; at every step the
+// column passes of each class, then one coefficient row launch whose flat
+// work list covers the row blocks of all classes, largest first).  An autotuner
 // picks each class's schedule by timing the candidates on the caller's
 // buffers: the chunk size (the number of subband pairs per pass launch,
 // which trades launch count against Infinity Cache residency of the
@@ -9,8 +12,9 @@
 // accumulation (one or two images per block) and whether small grids split
 // the subband-pair loop over blocks, and for classes with 1024-point lines
 // the line plan (values per thread of those lines' FFTs, kernels2d.hip).
-// Results are cached in a small text file, one line per class: key, chunk
-// bytes, images per block, split, line plan.
+// It then times the two schedules.  Results are cached in a small text file,
+// one line per class (key, chunk bytes, images per block, split, line plan)
+// and one for the schedule.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,6 +32,8 @@
 struct sl_multi {
   std::vector<sl_system *> sys;
   std::vector<int> counts;
+  int schedule = 0;   // 0: one multi-class coefficient row launch per step where
+                      // supported, else per class; 1: per class (graph branches)
   std::vector<size_t> ws_off;
   size_t ws_total = 0;
   std::vector<hipStream_t> side;
@@ -63,6 +69,30 @@ struct Bufs {
   char *ws;
 };
 
+std::vector<sl::MultiClass2D> classes(sl_multi *m, const Bufs &b) {
+  std::vector<sl::MultiClass2D> c(m->sys.size());
+  for (size_t s = 0; s < m->sys.size(); ++s) {
+    size_t wsb = 0;
+    sl_workspace_size(m->sys[s], m->counts[s], &wsb);
+    c[s] = {m->sys[s], m->counts[s], b.x ? b.x[s] : nullptr, b.coeffs[s],
+            b.scales ? b.scales[s] : nullptr, b.sigma ? b.sigma[s] : nullptr,
+            b.out ? b.out[s] : nullptr, b.ws + m->ws_off[s], wsb};
+  }
+  return c;
+}
+
+// the multi-class schedule applies: chosen, and every class supports it
+bool use_multi(sl_multi *m) {
+  if (m->schedule != 0 || m->sys.size() > (size_t)sl::kMaxMultiClasses) return false;
+  Bufs none{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  std::vector<void *> dummy(m->sys.size(), nullptr);
+  none.coeffs = dummy.data();
+  auto c = classes(m, none);
+  return sl::multi2d_supported(c.data(), (int)c.size());
+}
+
+int run_all(sl_multi *m, const Bufs &b, int what, hipStream_t st);
+
 int run_class(sl_multi *m, int s, const Bufs &b, int what, hipStream_t st) {
   void *ws = b.ws + m->ws_off[s];
   size_t wsb = 0;
@@ -75,6 +105,18 @@ int run_class(sl_multi *m, int s, const Bufs &b, int what, hipStream_t st) {
     rc = sl_inverse(m->sys[s], b.coeffs[s], b.scales ? b.scales[s] : nullptr, m->counts[s],
                     b.sigma ? b.sigma[s] : nullptr, b.K, b.out[s], ws, wsb, st);
   return rc;
+}
+
+int run_all(sl_multi *m, const Bufs &b, int what, hipStream_t st) {
+  if (use_multi(m)) {
+    auto c = classes(m, b);
+    return sl::run_multi2d(c.data(), (int)c.size(), what, b.K, st);
+  }
+  for (size_t s = 0; s < m->sys.size(); ++s) {
+    int rc = run_class(m, (int)s, b, what, st);
+    if (rc) return rc;
+  }
+  return SL_OK;
 }
 
 std::string tune_key(const sl_system *s, int count) {
@@ -164,6 +206,19 @@ int sl_system_block_shape(const sl_system *s, int *inv_images, int *split_pairs)
   return SL_OK;
 }
 
+int sl_multi_set_schedule(sl_multi *m, int per_class) {
+  if (!m || (per_class != 0 && per_class != 1))
+    return sl::set_error(SL_EINVAL, "per_class must be 0 or 1");
+  m->schedule = per_class;
+  return SL_OK;
+}
+
+int sl_multi_schedule(sl_multi *m, int *multi_class_rows) {
+  if (!m || !multi_class_rows) return sl::set_error(SL_EINVAL, "NULL argument");
+  *multi_class_rows = use_multi(m) ? 1 : 0;
+  return SL_OK;
+}
+
 int sl_multi_create(sl_system *const *systems, const int *counts, int n_classes, sl_multi **out) {
   if (!systems || !counts || !out || n_classes < 1 || n_classes > 64)
     return sl::set_error(SL_EINVAL, "bad arguments to sl_multi_create");
@@ -207,11 +262,7 @@ int sl_multi_run(sl_multi *m, int what, const float *const *x_dev, void *const *
   layout(m);
   if (workspace_bytes < m->ws_total) return sl::set_error(SL_ENOMEM, "workspace too small");
   Bufs b{x_dev, coeffs_dev, scales_dev, sigma_dev, K_host, out_dev, (char *)workspace_dev};
-  for (size_t s = 0; s < m->sys.size(); ++s) {
-    int rc = run_class(m, (int)s, b, what, (hipStream_t)stream);
-    if (rc) return rc;
-  }
-  return SL_OK;
+  return run_all(m, b, what, (hipStream_t)stream);
 }
 
 int sl_multi_autotune(sl_multi *m, const float *const *x_dev, void *const *coeffs_dev,
@@ -275,6 +326,48 @@ int sl_multi_autotune(sl_multi *m, const float *const *x_dev, void *const *coeff
     apply(sy, best_s);
     cache[key] = best_s;
   }
+  // the schedule across classes: per class (graph branches), or one
+  // multi-class coefficient row launch per step (1024-point classes then take
+  // the line plan that launch needs); cached under the classes' keys
+  std::string skey = "schedule";
+  for (size_t s = 0; s < m->sys.size(); ++s) skey += ";" + tune_key(m->sys[s], m->counts[s]);
+  auto sit = cache.find(skey);
+  if (rc == SL_OK && sit != cache.end()) {
+    m->schedule = sit->second.split;
+    if (m->schedule == 0)
+      for (auto *sy : m->sys)
+        if (has_em2(sy)) sy->line_em = 2;
+  } else if (rc == SL_OK) {
+    std::vector<int> em_was;
+    for (auto *sy : m->sys) em_was.push_back(sy->line_em);
+    auto time_all = [&](float &ms) -> int {
+      int r = run_all(m, b, 3, st);   // warm-up
+      if (r) return r;
+      (void)hipEventRecord(e0, st);
+      for (int k = 0; k < 3 && r == SL_OK; ++k) r = run_all(m, b, 3, st);
+      (void)hipEventRecord(e1, st);
+      if (r) return r;
+      (void)hipEventSynchronize(e1);
+      return hipEventElapsedTime(&ms, e0, e1) == hipSuccess ? SL_OK : SL_EHIP;
+    };
+    float t_class = 1e30f, t_multi = 1e30f;
+    m->schedule = 1;
+    rc = time_all(t_class);
+    if (rc == SL_OK) {
+      m->schedule = 0;
+      for (auto *sy : m->sys)
+        if (has_em2(sy)) sy->line_em = 2;
+      if (use_multi(m)) rc = time_all(t_multi);
+    }
+    if (rc == SL_OK && t_multi < t_class) {
+      m->schedule = 0;
+    } else {
+      m->schedule = 1;
+      for (size_t s = 0; s < m->sys.size(); ++s) m->sys[s]->line_em = em_was[s];
+    }
+    Sched sv{0, 0, m->schedule, 0};
+    cache[skey] = sv;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
@@ -315,13 +408,19 @@ int sl_multi_graph_build(sl_multi *m, int what, const float *const *x_dev,
   // per-pass timing events must not be recorded into the graph
   const bool capturing_was = sl::set_capturing(true);
   int rc = SL_OK;
-  hipError_t e = hipEventRecord(m->fork, cs);
-  for (int s = 1; s < n && e == hipSuccess; ++s) e = hipStreamWaitEvent(m->side[s], m->fork, 0);
-  for (int s = 0; s < n && e == hipSuccess && rc == SL_OK; ++s) {
-    rc = run_class(m, s, b, what, m->side[s]);
-    if (rc == SL_OK && s > 0) {
-      e = hipEventRecord(m->join[s], m->side[s]);
-      if (e == hipSuccess) e = hipStreamWaitEvent(cs, m->join[s], 0);
+  hipError_t e = hipSuccess;
+  if (use_multi(m)) {
+    // one stream: the per-class passes and the multi-class row launches in order
+    rc = run_all(m, b, what, cs);
+  } else {
+    e = hipEventRecord(m->fork, cs);
+    for (int s = 1; s < n && e == hipSuccess; ++s) e = hipStreamWaitEvent(m->side[s], m->fork, 0);
+    for (int s = 0; s < n && e == hipSuccess && rc == SL_OK; ++s) {
+      rc = run_class(m, s, b, what, m->side[s]);
+      if (rc == SL_OK && s > 0) {
+        e = hipEventRecord(m->join[s], m->side[s]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cs, m->join[s], 0);
+      }
     }
   }
   sl::set_capturing(capturing_was);

@@ -59,4 +59,26 @@ int hip_error(hipError_t e, const char *what);
 // mark the calling thread as capturing a graph (per-pass timing events are
 // then not recorded); returns the previous state
 bool set_capturing(bool on);
+
+// One size class of an uneven 2D batch for run_multi2d: its system, image
+// count, buffers and its own workspace slot.
+struct MultiClass2D {
+  const sl_system *s;
+  int B;
+  const float *x;
+  void *coef;
+  float *scales;
+  const float *sigma;
+  float *out;
+  void *ws;
+  size_t ws_bytes;
+};
+// Whether run_multi2d can take these classes (2D systems of one storage type
+// whose row lengths have a multi-class row pass).
+bool multi2d_supported(const MultiClass2D *cls, int n);
+// Forward (what & 1) and / or inverse (what & 2, hard threshold with K when
+// a class has sigma) of every class on one stream: per class the spectrum
+// and column passes, and for each schedule step one coefficient row launch
+// across all classes (launch_rows_multi).
+int run_multi2d(const MultiClass2D *cls, int n, int what, const float *K, hipStream_t st);
 }

@@ -51,7 +51,9 @@ def _setup(dtype="f16"):
 def _check(systems, host, coeffs, scales, outs, tol):
     for s, imgs, c, sc, o in zip(systems, host, coeffs, scales, outs):
         orc = S.build_2d(s.dims, J, LEVELS)
-        cd = c.float().cpu().numpy().astype(np.float64) * sc.cpu().numpy()[:, :, None, None]
+        cd = c.float().cpu().numpy().astype(np.float64)
+        if c.dtype != torch.float32:
+            cd = cd * sc.cpu().numpy()[:, :, None, None]
         for k in range(imgs.shape[0]):
             assert rel(cd[k], T.forward(imgs[k], orc.filters)) < tol
             assert rel(o[k].cpu().numpy(), imgs[k]) < tol
@@ -116,11 +118,17 @@ def test_uneven_autotune(tmp_path):
     m.autotune(xs, coeffs, scales, outs, ws, cache_path=cache)
     assert os.path.exists(cache)
     lines = [ln.split() for ln in open(cache).read().split("\n") if ln.strip()]
-    assert len(lines) == len(SIZES)
-    # key, chunk bytes, images per inverse block (1 or 2), pair-loop split (0 or 1)
+    sched = [ln for ln in lines if ln[0].startswith("schedule;")]
+    lines = [ln for ln in lines if not ln[0].startswith("schedule;")]
+    assert len(lines) == len(SIZES) and len(sched) == 1
+    # key, chunk bytes, images per inverse block (1 or 2), pair-loop split (0 or 1),
+    # line plan (1 or 2)
     for ln in lines:
-        assert len(ln) == 4 and int(ln[1]) >= 1 << 20
-        assert int(ln[2]) in (1, 2) and int(ln[3]) in (0, 1)
+        assert len(ln) == 5 and int(ln[1]) >= 1 << 20
+        assert int(ln[2]) in (1, 2) and int(ln[3]) in (0, 1) and int(ln[4]) in (1, 2)
+    # the schedule across classes: 0 multi-class row launches, 1 per class
+    assert int(sched[0][3]) in (0, 1)
+    assert m.multi_class_rows() == (int(sched[0][3]) == 0)
     m.run(3, xs, coeffs, scales, outs=outs, workspace=ws)
     torch.cuda.synchronize()
     _check(systems, host, coeffs, scales, outs, 2e-3)
@@ -203,3 +211,50 @@ def test_line_plan_1024(dtype):
     o = S.build_2d(dims, 2, [1, 1])
     assert rel(outs[2][0][0], T.forward(xs[0], o.filters)) < tol
     assert rel(outs[2][1], xs) < tol
+
+
+@pytest.mark.parametrize("dtype", ["f16", "f32"])
+def test_multi_class_row_schedule(dtype):
+    # the multi-class schedule (one coefficient row launch over the row blocks
+    # of all classes per step) computes every row with the same plan and line
+    # FFT as the per-class launches: with 16-bit storage (the same prefetching
+    # row kernels) results equal bit for bit; with float32 storage the
+    # per-class launches use the single-group row kernels, which the compiler
+    # contracts differently, so they agree to float32 rounding (<= 1e-6).  The
+    # graph replays equal the eager multi-class run bit for bit, and the
+    # results match the oracle.
+    def same(a, b):
+        if dtype == "f16":
+            return torch.equal(a, b)
+        return rel(a.cpu().numpy(), b.cpu().numpy()) <= 1e-6
+    print(f"case: multi-class row schedule, {dtype}", flush=True)
+    m, systems, host, xs, coeffs, scales, outs, ws = _setup(dtype)
+    assert m.multi_class_rows()
+    m.run(3, xs, coeffs, scales, outs=outs, workspace=ws)
+    torch.cuda.synchronize()
+    ref_c = [c.clone() for c in coeffs]
+    ref_o = [o.clone() for o in outs]
+    m.set_schedule(True)
+    assert not m.multi_class_rows()
+    m.run(3, xs, coeffs, scales, outs=outs, workspace=ws)
+    torch.cuda.synchronize()
+    for a, b in zip(coeffs, ref_c):
+        assert same(a, b)
+    for a, b in zip(outs, ref_o):
+        assert same(a, b)
+    m.set_schedule(False)
+    assert m.multi_class_rows()
+    m.graph_build(3, xs, coeffs, scales, outs=outs, workspace=ws)
+    for rep in range(2):
+        for c in coeffs:
+            c.zero_()
+        for o in outs:
+            o.zero_()
+        torch.cuda.synchronize()
+        m.graph_launch()
+        torch.cuda.synchronize()
+        for a, b in zip(coeffs, ref_c):
+            assert torch.equal(a, b), rep
+        for a, b in zip(outs, ref_o):
+            assert torch.equal(a, b), rep
+    _check(systems, host, coeffs, scales, outs, 2e-3 if dtype == "f16" else 1e-5)
