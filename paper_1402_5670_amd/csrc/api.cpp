@@ -167,8 +167,8 @@ sl::Sys3D view3d(const sl_system *s) {
   v.W = (int)s->cfg.dims[2];
   v.R = s->R;
   v.dtype = s->cfg.dtype;
-  v.subs = s->d_subs3;
-  v.tab = s->d_tab3;
+  v.pairs = s->d_zpairs;
+  v.tab = s->d_ztab;
   v.psi = s->d_psi;
   v.twD = s->d_tw.at(v.D);
   return v;
@@ -772,43 +772,124 @@ int build_system_impl(const sl_config *cfg, bool wavelet, sl_system **out) {
     return rc;
   }
   if (is3d) {
-    // factor tables: lowpass lines per axis, g lines per (scale, axis) and the
-    // Phi planes per (scale, shear, main axis, secondary axis)
+    // Per pair of subbands (a, b = a + 1), the filters along the z lines as
+    // float2 (value for a, value for b) tables, so that a z line reads both
+    // filters of its pair with one load per voxel and factor (Section 3.3.2:
+    // every 3D filter is a product of factors along the pyramid's main axis
+    // and along each secondary axis).  psi_i(z, y, x) = C_i(y, x) X_i(z, x) Y_i(z, y):
+    //   lowpass   C = h(x) h(y),            Y = h(z)   (the same for every y)
+    //   main x    C = g(x) Phi_k1(x, y),     X = Phi_k2(x, z)
+    //   main y    C = g(y) Phi_k1(y, x),     Y = Phi_k2(y, z)
+    //   main z    C = 1,   X = Phi_k1(z, x), Y = g(z) Phi_k2(z, y)
+    // A factor a subband lacks is 1; the missing partner of an odd R has C = 0.
+    // Every pair has a C block [H][W], and X [D][W] and Y [D][H] blocks when
+    // one of its subbands has that factor.  A block interleaves two factors;
+    // the same two factors recur in many pairs (consecutive subbands share k1,
+    // and a pair's (k2, k2 + 1) recurs for every k1), so each distinct
+    // combination is stored once and pairs point to it: neighbouring pairs then
+    // find most of their blocks in L2 instead of streaming a fresh block from
+    // HBM per pair.  Products are formed in FP64 and rounded once.
     slh::Tables3D t;
     slh::build_tables_3d(s->cfg, t);
-    std::vector<float> tab;
-    auto push = [&](const std::vector<double> &v) {
-      int off = (int)tab.size();
-      for (double d : v) tab.push_back((float)d);
+    const int D = s->cfg.n(3), H = s->cfg.n(2), W = s->cfg.n(1);
+    // factor of one subband in one role: kind 0 = 1, 1 = 0, 2 = lowpass,
+    // 3..5 = pyramid with main axis x, y, z; (j, k) pick g and Phi
+    struct FKey {
+      int kind, j, k;
+      bool operator<(const FKey &o) const {
+        return kind != o.kind ? kind < o.kind : j != o.j ? j < o.j : k < o.k;
+      }
+    };
+    enum { kOne = 0, kZero = 1, kLow = 2 };
+    auto fkey = [&](int i, int role) -> FKey {   // role 0 = C, 1 = X, 2 = Y
+      if (i >= R) return FKey{role == 0 ? kZero : kOne, 0, 0};
+      const auto &b = bank.subbands[i];
+      if (b.cone == 0) return (role == 1) ? FKey{kOne, 0, 0} : FKey{kLow, 0, 0};
+      const int kind = 2 + b.cone;   // 3, 4, 5 for main axis x, y, z
+      if (role == 0) return b.cone == 3 ? FKey{kOne, 0, 0} : FKey{kind, b.j, b.k1};
+      if (role == 1) return b.cone == 2 ? FKey{kOne, 0, 0} : FKey{kind, b.j, b.cone == 3 ? b.k1 : b.k2};
+      return b.cone == 1 ? FKey{kOne, 0, 0} : FKey{kind, b.j, b.k2};
+    };
+    // value of a factor at (v, u): C (y, x), X (z, x), Y (z, y); planes are
+    // stored [secondary][main]
+    struct Fac {
+      int kind, am;
+      const double *g, *pl;
+    };
+    auto resolve = [&](int role, const FKey &f) -> Fac {
+      Fac r{f.kind, 0, nullptr, nullptr};
+      if (f.kind < 3) return r;
+      r.am = f.kind - 2;
+      r.g = t.g[(size_t)f.j * 3 + r.am - 1].data();
+      // secondary axis of the plane, [role][main axis]: C uses Phi(x, y) or
+      // Phi(y, x), X uses Phi(x, z) or Phi(z, x), Y uses Phi(y, z) or Phi(z, y)
+      static const int sec[3][4] = {{0, 2, 1, 0}, {0, 3, 0, 1}, {0, 0, 3, 2}};
+      const int sa = sec[role][r.am];
+      r.pl = t.planes[t.find(f.j, f.k, r.am, sa)].data();
+      return r;
+    };
+    auto fval = [&](int role, const Fac &f, int v, int u) -> double {
+      if (f.kind == kOne) return 1.0;
+      if (f.kind == kZero) return 0.0;
+      if (f.kind == kLow) return role == 0 ? t.low[0][u] * t.low[1][v] : t.low[2][v];
+      if (role == 0) {
+        if (f.am == 1) return f.g[u] * f.pl[(size_t)v * W + u];
+        return f.g[v] * f.pl[(size_t)u * H + v];
+      }
+      if (role == 1) {
+        if (f.am == 1) return f.pl[(size_t)v * W + u];
+        return f.pl[(size_t)u * D + v];
+      }
+      if (f.am == 2) return f.pl[(size_t)v * H + u];
+      return f.g[v] * f.pl[(size_t)u * D + v];
+    };
+    struct Combo {
+      int role;
+      FKey a, b;
+      bool operator<(const Combo &o) const {
+        if (role != o.role) return role < o.role;
+        if (a < o.a || o.a < a) return a < o.a;
+        return b < o.b;
+      }
+    };
+    const size_t rows[3] = {(size_t)H, (size_t)D, (size_t)D};
+    const size_t cols[3] = {(size_t)W, (size_t)W, (size_t)H};
+    std::map<Combo, long long> combo_off;
+    std::vector<Combo> combos;
+    size_t total = 0;
+    auto place = [&](const Combo &cb) -> long long {
+      auto it = combo_off.find(cb);
+      if (it != combo_off.end()) return it->second;
+      const long long off = (long long)total;
+      total += rows[cb.role] * cols[cb.role];
+      combo_off.emplace(cb, off);
+      combos.push_back(cb);
       return off;
     };
-    int low_off[4] = {0, 0, 0, 0};
-    for (int ax = 1; ax <= 3; ++ax) low_off[ax] = push(t.low[ax - 1]);
-    std::vector<int> g_off(t.g.size()), p_off(t.planes.size());
-    for (size_t q = 0; q < t.g.size(); ++q) g_off[q] = push(t.g[q]);
-    for (size_t q = 0; q < t.planes.size(); ++q) p_off[q] = push(t.planes[q]);
-    static const int axes[4][3] = {{1, 2, 3}, {1, 2, 3}, {2, 1, 3}, {3, 1, 2}};
-    std::vector<sl::Sub3D> subs3(R);
-    for (int i = 0; i < R; ++i) {
-      const auto &b = bank.subbands[i];
-      sl::Sub3D d{};
-      d.cone = b.cone;
-      if (b.cone == 0) {
-        d.g_off = low_off[1];
-        d.p1_off = low_off[2];
-        d.p2_off = low_off[3];
-      } else {
-        d.am = axes[b.cone][0];
-        d.s1 = axes[b.cone][1];
-        d.s2 = axes[b.cone][2];
-        d.g_off = g_off[(size_t)b.j * 3 + d.am - 1];
-        d.p1_off = p_off[t.find(b.j, b.k1, d.am, d.s1)];
-        d.p2_off = p_off[t.find(b.j, b.k2, d.am, d.s2)];
-        d.n_main = s->cfg.n(d.am);
+    const int P = (R + 1) / 2;
+    std::vector<sl::ZPair> zpairs(P);
+    for (int p = 0; p < P; ++p) {
+      const int a = 2 * p, b = 2 * p + 1;
+      sl::ZPair &z = zpairs[p];
+      z.c = place(Combo{0, fkey(a, 0), fkey(b, 0)});
+      z.x = z.y = -1;
+      for (int role = 1; role <= 2; ++role) {
+        const Combo cb{role, fkey(a, role), fkey(b, role)};
+        if (cb.a.kind == kOne && cb.b.kind == kOne) continue;   // neither has it
+        (role == 1 ? z.x : z.y) = place(cb);
       }
-      subs3[i] = d;
     }
-    if ((rc = dev_upload(s, tab, &s->d_tab3)) || (rc = dev_upload(s, subs3, &s->d_subs3))) {
+    std::vector<float2> ztab(total);
+    slh::parallel_run((int64_t)combos.size(), [&](int64_t q) {
+      const Combo &cb = combos[q];
+      float2 *dst = ztab.data() + combo_off.at(cb);
+      const Fac fa = resolve(cb.role, cb.a), fb = resolve(cb.role, cb.b);
+      for (size_t v = 0; v < rows[cb.role]; ++v)
+        for (size_t u = 0; u < cols[cb.role]; ++u)
+          dst[v * cols[cb.role] + u] = make_float2((float)fval(cb.role, fa, (int)v, (int)u),
+                                                   (float)fval(cb.role, fb, (int)v, (int)u));
+    });
+    if ((rc = dev_upload(s, ztab, &s->d_ztab)) || (rc = dev_upload(s, zpairs, &s->d_zpairs))) {
       sl_free_system(s);
       return rc;
     }

@@ -143,15 +143,18 @@ hipError_t launch_xcd_inv(const Sys2D &s, const float *coef, const ThrArgs &thr,
 //   lowpass (cone 0): tab[g_off + x] * tab[p1_off + y] * tab[p2_off + z]
 //   otherwise: g[xi_am] * plane1[xi_s1][xi_am] * plane2[xi_s2][xi_am] with
 //   axes numbered 1 = x (W), 2 = y (H), 3 = z (D) and planes of row length n_main.
-struct Sub3D {
-  int cone, am, s1, s2;
-  int g_off, p1_off, p2_off, n_main;
+// Filters of subband pair p (a = 2p, b = 2p + 1) along the z line of voxel
+// column (y, x): psi(z) = C[c + y W + x] * X[x + z W] * Y[y + z H] (float2:
+// the value for a, the value for b), with X or Y absent (= 1) when the
+// offset is negative.  Offsets count float2 elements of Sys3D::tab.
+struct ZPair {
+  long long c, x, y;
 };
 
 struct Sys3D {
   int D, H, W, R, dtype;
-  const Sub3D *subs;          // [R]
-  const float *tab;           // factor tables
+  const ZPair *pairs;         // [(R + 1) / 2]
+  const float2 *tab;          // per-pair factor blocks
   const float *psi;           // [D][H][W] Psi_hat
   const float2 *twD;
 };

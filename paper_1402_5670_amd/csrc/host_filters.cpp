@@ -97,6 +97,8 @@ std::vector<double> default_qmf_half() {
 
 }  // namespace
 
+void parallel_run(int64_t n, const std::function<void(int64_t)> &fn) { parallel_for(n, fn); }
+
 bool fft_size_supported(int64_t n) {
   // 2^a 3^b with a >= 2, b <= 1, 8 <= n <= 1024: the lengths the device FFT
   // is instantiated for

@@ -19,6 +19,7 @@
 
 #include <cstdint>
 #include <string>
+#include <functional>
 #include <vector>
 
 #include "../../include/shearlet.h"
@@ -96,6 +97,9 @@ struct Tables3D {
   int find(int j, int k, int main_axis, int sec_axis) const;
 };
 void build_tables_3d(const Config &c, Tables3D &t);
+
+// fn(0) .. fn(n - 1) on the host's hardware threads (at most 32)
+void parallel_run(int64_t n, const std::function<void(int64_t)> &fn);
 
 // Simple FP64 complex FFT for sizes 2^a 3^b (host; used for l1 norms).
 void host_dft_inplace(std::vector<double> &re, std::vector<double> &im, int sign);

@@ -3,11 +3,12 @@
 // A volume [D][H][W] is transformed axis by axis with the line kernels of the
 // 2D path applied to reshaped views: x lines are rows of a (D*H) x W image,
 // y lines are columns of D images of H x W, z lines are columns of one
-// D x (H*W) image.  Only the z pass is specific to 3D: it generates the
-// filters on the fly from their factors
+// D x (H*W) image.  Only the z pass is specific to 3D: it forms the filters
+// on the fly from their factors
 //     psi_hat(xi) = g_hat_{J-j}(xi_a) Phi_hat_{j,k1}(xi_a, xi_s1) Phi_hat_{j,k2}(xi_a, xi_s2)
-// (main axis a and secondary axes s1, s2 of the pyramid), so the R full
-// filter volumes never exist in memory.
+// (main axis a and secondary axes s1, s2 of the pyramid), regrouped per pair
+// of subbands into one (y, x) block and (z, x), (z, y) blocks (ZPair), so the
+// R full filter volumes never exist in memory.
 #include <hip/hip_runtime.h>
 
 #include "dispatch.hpp"
@@ -23,61 +24,60 @@ struct Tile3 {
   static constexpr int THREADS = M * NT;
 };
 
-// psi_hat_i along the z line of voxel column (y, x).  Unless z is the
-// pyramid's main axis, only one factor varies along the line:
-//   psi_hat(z) = c * tab[base + z * stride],
-// with c the product of the two factors that are constant on the line (the
-// lowpass: g_hat(x) h_hat(y) times h_hat(z)).  With z as the main axis all
-// three factors vary: psi_hat(z) = tab[g + z] * tab[p1 + z] * tab[p2 + z].
-struct ZLine {
-  float c;
-  int base, stride;   // one varying factor (main axis x or y, or lowpass)
-  int g, p1, p2;      // main axis z (stride < 0 marks this case)
+// Filters of one pair along one z line, from the pair's blocks of the factor
+// table (ZPair): psi(z) = C * X[z W + x] * Y[z H + y], one float2 load per
+// present factor and voxel (the lanes of a column tile, at consecutive x,
+// read consecutive elements of X and one element of Y).  Value e of thread t
+// sits at z = t + e NT: the lane's part of the address is one 32-bit byte
+// offset (row t), the step e NT rows is wave-uniform, so no per-value
+// addresses stay live across the pair loop.
+template <bool HX, bool HY>
+struct ZFilt {
+  const char *X, *Y;    // pair blocks (uniform)
+  size_t sx, sy;        // bytes per value step (uniform)
+  unsigned ox, oy;      // lane offsets of rows t
+  float2 c;
+  __device__ __forceinline__ float2 operator()(int e) const {
+    float2 f = c;
+    if constexpr (HX) {
+      const float2 q = *(const float2 *)(X + e * sx + ox);
+      f.x *= q.x;
+      f.y *= q.y;
+    }
+    if constexpr (HY) {
+      const float2 q = *(const float2 *)(Y + e * sy + oy);
+      f.x *= q.x;
+      f.y *= q.y;
+    }
+    return f;
+  }
 };
 
-__device__ __forceinline__ ZLine zline(const Sub3D &d, const float *__restrict__ tab, int y,
-                                       int x) {
-  ZLine L;
-  L.g = L.p1 = L.p2 = 0;
-  if (d.cone == 0) {
-    L.c = tab[d.g_off + x] * tab[d.p1_off + y];
-    L.base = d.p2_off;
-    L.stride = 1;
-    return L;
-  }
-  const int idx[4] = {0, x, y, 0};
-  if (d.am == 3) {
-    L.c = 1.f;
-    L.base = 0;
-    L.stride = -1;
-    L.g = d.g_off;
-    L.p1 = d.p1_off + idx[d.s1] * d.n_main;
-    L.p2 = d.p2_off + idx[d.s2] * d.n_main;
-    return L;
-  }
-  const int im = idx[d.am];
-  if (d.s1 == 3) {
-    L.c = tab[d.g_off + im] * tab[d.p2_off + idx[d.s2] * d.n_main + im];
-    L.base = d.p1_off + im;
-  } else {
-    L.c = tab[d.g_off + im] * tab[d.p1_off + idx[d.s1] * d.n_main + im];
-    L.base = d.p2_off + im;
-  }
-  L.stride = d.n_main;
-  return L;
-}
-
-__device__ __forceinline__ float zline_at(const ZLine &L, const float *__restrict__ tab, int z) {
-  if (L.stride >= 0) return L.c * tab[L.base + z * L.stride];
-  return tab[L.g + z] * tab[L.p1 + z] * tab[L.p2 + z];
+// Runs body(filter) with the pair's filter functor.  Which factors a pair has
+// is uniform over the block, hence one instance of the body per combination.
+// c is the pair's C at this column, which the caller loads one pair ahead.
+template <int NT, class Body>
+__device__ __forceinline__ void with_zfilters(const float2 *__restrict__ tab, const ZPair &zp,
+                                              float2 c, int t, int y, int x, int H, int W,
+                                              Body &&body) {
+  const char *X = (const char *)(tab + zp.x), *Y = (const char *)(tab + zp.y);
+  const size_t sx = (size_t)NT * W * sizeof(float2), sy = (size_t)NT * H * sizeof(float2);
+  const unsigned ox = (unsigned)(t * W + x) * (unsigned)sizeof(float2);
+  const unsigned oy = (unsigned)(t * H + y) * (unsigned)sizeof(float2);
+  if (zp.x >= 0 && zp.y >= 0)
+    body(ZFilt<true, true>{X, Y, sx, sy, ox, oy, c});
+  else if (zp.x >= 0)
+    body(ZFilt<true, false>{X, Y, sx, sy, ox, oy, c});
+  else
+    body(ZFilt<false, true>{X, Y, sx, sy, ox, oy, c});
 }
 
 // z pass of the forward transform: F * (psi_a + i psi_b), inverse DFT along z.
 // Columns are the H*W voxels of a z-slice; grid (ceil(HW/M), nb).
 template <int N>
 __global__ void __launch_bounds__(Tile3<N>::THREADS)
-k_z_filter_ifft(const float2 *__restrict__ F, const Sub3D *__restrict__ subs,
-                const float *__restrict__ tab, float2 *__restrict__ T, int H, int W, int R,
+k_z_filter_ifft(const float2 *__restrict__ F, const ZPair *__restrict__ pairs,
+                const float2 *__restrict__ tab, float2 *__restrict__ T, int H, int W, int R,
                 int b0, int p0, int np, const float2 *__restrict__ tw) {
   constexpr int NT = Tile3<N>::NT, M = Tile3<N>::M, E = Tile3<N>::E;
   __shared__ float2 lds[M * N];
@@ -94,18 +94,18 @@ k_z_filter_ifft(const float2 *__restrict__ F, const Sub3D *__restrict__ subs,
   float2 f[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) f[e] = F[(size_t)b * vol + (size_t)(t + e * NT) * HW + cc];
+  float2 cn = (tab + pairs[p0].c)[y * W + x];
   for (int pp = 0; pp < np; ++pp) {
-    const int ia = 2 * (p0 + pp), ib = ia + 1;
-    const ZLine la = zline(subs[ia], tab, y, x);
-    const ZLine lb = zline(subs[ib < R ? ib : ia], tab, y, x);
+    const float2 c = cn;
+    if (pp + 1 < np) cn = (tab + pairs[p0 + pp + 1].c)[y * W + x];
     float2 v[E];
+    with_zfilters<NT>(tab, pairs[p0 + pp], c, t, y, x, H, W, [&](const auto &psi) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int z = t + e * NT;
-      const float a = zline_at(la, tab, z);
-      const float bb = ib < R ? zline_at(lb, tab, z) : 0.f;
-      v[e] = make_float2(f[e].x * a - f[e].y * bb, f[e].y * a + f[e].x * bb);
-    }
+      for (int e = 0; e < E; ++e) {
+        const float2 q = psi(e);
+        v[e] = make_float2(f[e].x * q.x - f[e].y * q.y, f[e].y * q.x + f[e].x * q.y);
+      }
+    });
     fft_line_p<Plan<N>, true>(v, t, LdsLine{lds + m, M}, TwLds{twl});
     if (ok) {
       float2 *To = T + ((size_t)blockIdx.y * np + pp) * vol + col;
@@ -120,8 +120,8 @@ k_z_filter_ifft(const float2 *__restrict__ F, const Sub3D *__restrict__ subs,
 // by Psi_hat and applies the inverse DFT along z.
 template <int N>
 __global__ void __launch_bounds__(Tile3<N>::THREADS)
-k_z_fft_acc(const float2 *__restrict__ U, const Sub3D *__restrict__ subs,
-            const float *__restrict__ tab, const float *__restrict__ psi, float2 *__restrict__ ACC,
+k_z_fft_acc(const float2 *__restrict__ U, const ZPair *__restrict__ pairs,
+            const float2 *__restrict__ tab, const float *__restrict__ psi, float2 *__restrict__ ACC,
             int H, int W, int R, int b0, int p0, int np, int first, int last,
             const float2 *__restrict__ tw) {
   constexpr int NT = Tile3<N>::NT, M = Tile3<N>::M, E = Tile3<N>::E;
@@ -141,23 +141,23 @@ k_z_fft_acc(const float2 *__restrict__ U, const Sub3D *__restrict__ subs,
 #pragma unroll
   for (int e = 0; e < E; ++e)
     acc[e] = first ? make_float2(0.f, 0.f) : accp[(size_t)(t + e * NT) * HW];
+  float2 cn = (tab + pairs[p0].c)[y * W + x];
   for (int pp = 0; pp < np; ++pp) {
-    const int ia = 2 * (p0 + pp), ib = ia + 1;
+    const float2 c = cn;
+    if (pp + 1 < np) cn = (tab + pairs[p0 + pp + 1].c)[y * W + x];
     const float2 *Ui = U + ((size_t)blockIdx.y * np + pp) * vol + cc;
     float2 v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = stream_load(&Ui[(size_t)(t + e * NT) * HW]);
     fft_line_p<Plan<N>, false>(v, t, LdsLine{lds + m, M}, TwLds{twl});
-    const ZLine la = zline(subs[ia], tab, y, x);
-    const ZLine lb = zline(subs[ib < R ? ib : ia], tab, y, x);
+    with_zfilters<NT>(tab, pairs[p0 + pp], c, t, y, x, H, W, [&](const auto &psi) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int z = t + e * NT;
-      const float a = zline_at(la, tab, z);
-      const float bb = ib < R ? zline_at(lb, tab, z) : 0.f;
-      acc[e].x += a * v[e].x + bb * v[e].y;
-      acc[e].y += a * v[e].y - bb * v[e].x;
-    }
+      for (int e = 0; e < E; ++e) {
+        const float2 q = psi(e);
+        acc[e].x += q.x * v[e].x + q.y * v[e].y;
+        acc[e].y += q.x * v[e].y - q.y * v[e].x;
+      }
+    });
   }
   if (last) {
     const float *ps = psi + cc;
@@ -184,7 +184,7 @@ hipError_t launch_z_filter_ifft(const Sys3D &s, const float2 *F, float2 *T, Chun
 #define X(N)                                                                                  \
   case N:                                                                                     \
     hipLaunchKernelGGL(k_z_filter_ifft<N>, dim3((HW + Tile3<N>::M - 1) / Tile3<N>::M, c.nb),   \
-                       dim3(Tile3<N>::THREADS), 0, st, F, s.subs, s.tab, T, s.H, s.W, s.R, c.b0, \
+                       dim3(Tile3<N>::THREADS), 0, st, F, s.pairs, s.tab, T, s.H, s.W, s.R, c.b0, \
                        c.p0, c.np, s.twD);                                                    \
     break;
     SL_FOR_EACH_N(X)
@@ -202,7 +202,7 @@ hipError_t launch_z_fft_acc(const Sys3D &s, const float2 *U, float2 *ACC, Chunk 
 #define X(N)                                                                                  \
   case N:                                                                                     \
     hipLaunchKernelGGL(k_z_fft_acc<N>, dim3((HW + Tile3<N>::M - 1) / Tile3<N>::M, c.nb),       \
-                       dim3(Tile3<N>::THREADS), 0, st, U, s.subs, s.tab, s.psi, ACC, s.H, s.W, \
+                       dim3(Tile3<N>::THREADS), 0, st, U, s.pairs, s.tab, s.psi, ACC, s.H, s.W, \
                        s.R, c.b0, c.p0, c.np, (int)first, (int)last, s.twD);                  \
     break;
     SL_FOR_EACH_N(X)

@@ -33,8 +33,8 @@ struct sl_system {
   float *d_psi = nullptr;     // Psi_hat on the grid
   float *d_l2 = nullptr, *d_l1 = nullptr;
   int *d_jof = nullptr;
-  sl::Sub3D *d_subs3 = nullptr;   // 3D: per-subband factor descriptors
-  float *d_tab3 = nullptr;        // 3D: factor tables
+  sl::ZPair *d_zpairs = nullptr;  // 3D: per-pair offsets into d_ztab
+  float2 *d_ztab = nullptr;       // 3D: per-pair z-line filter factors
   std::map<int, float2 *> d_tw;
   std::vector<void *> allocs;
   // instantiated inpainting graphs, keyed by every argument they bake in
