@@ -270,6 +270,7 @@ int forward3d(const sl_system *s, const float *x, int batch, void *coef, float *
   const sl::Sys2D vz = view2d(s, D, H * W, D, 0);       // z lines per volume
   const sl::Sys2D vp = view2d(s, H, W, H, W);           // z-slices in LDS
   const bool plane = s->plane3d && sl::plane_supported(H, W);
+  const bool half = s->plane3d && !plane && sl::half_plane_supported(H, W);
   const float inv_vol = 1.0f / ((float)(D * H) * (float)W);
   const sl::Sys3D v3 = view3d(s);
   if (scaled) SL_LAUNCH(P_AUX, st, sl::launch_zero_u32(xmax, batch, st));
@@ -287,6 +288,8 @@ int forward3d(const sl_system *s, const float *x, int batch, void *coef, float *
       SL_LAUNCH(P_COLS_FILTER_IFFT, st, sl::launch_z_filter_ifft(v3, F, T, c, st));
       if (plane) {
         SL_LAUNCH(P_ROWS_COEF, st, sl::launch_plane_coef(vp, D, T, coef, scales, c, inv_vol, st));
+      } else if (half) {
+        SL_LAUNCH(P_ROWS_COEF, st, sl::launch_hplane_coef(vp, D, T, coef, scales, c, inv_vol, st));
       } else {
         SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, T, T, c.nb * c.np * D, true, st, true));
         SL_LAUNCH(P_ROWS_COEF, st, sl::launch_rows_coef(vr, T, coef, scales, c, st));
@@ -302,6 +305,7 @@ int inverse3d(const sl_system *s, const void *coef, const float *scales, int bat
   const sl::Sys2D vy = view2d(s, H, W, H, 0);
   const sl::Sys2D vp = view2d(s, H, W, H, W);
   const bool plane = s->plane3d && sl::plane_supported(H, W);
+  const bool half = s->plane3d && !plane && sl::half_plane_supported(H, W);
   const sl::Sys3D v3 = view3d(s);
   int nb, np;
   chunk_plan(s, batch, nb, np);
@@ -311,6 +315,8 @@ int inverse3d(const sl_system *s, const void *coef, const float *scales, int bat
       sl::Chunk c{b0, std::min(nb, batch - b0), p0, std::min(np, P - p0)};
       if (plane) {
         SL_LAUNCH(P_ROWS_COEF_FFT, st, sl::launch_plane_coef_fft(vp, D, coef, scales, U, c, thr, st));
+      } else if (half) {
+        SL_LAUNCH(P_ROWS_COEF_FFT, st, sl::launch_hplane_coef_fft(vp, D, coef, scales, U, c, thr, st));
       } else {
         SL_LAUNCH(P_ROWS_COEF_FFT, st, sl::launch_rows_coef_fft(vr, coef, scales, U, c, thr, st));
         SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, U, U, c.nb * c.np * D, false, st, true));

@@ -174,6 +174,14 @@ hipError_t launch_plane_coef(const Sys2D &s, int D, const float2 *T, void *coef,
 hipError_t launch_plane_coef_fft(const Sys2D &s, int D, const void *coef, const float *scales,
                                  float2 *U, Chunk c, const ThrArgs &thr, hipStream_t st);
 // T -> y IDFT, x IDFT, scale, threshold, x DFT, y DFT -> T (fused denoise)
+// Half-plane passes: slices too large for LDS, split in y into two halves
+// (one decimation-in-frequency step); forward and inverse only.  Results
+// agree with the line passes to float32 rounding.
+bool half_plane_supported(int H, int W);
+hipError_t launch_hplane_coef(const Sys2D &s, int D, const float2 *T, void *coef,
+                              const float *scales, Chunk c, float inv_n, hipStream_t st);
+hipError_t launch_hplane_coef_fft(const Sys2D &s, int D, const void *coef, const float *scales,
+                                  float2 *U, Chunk c, const ThrArgs &thr, hipStream_t st);
 hipError_t launch_plane_thr(const Sys2D &s, int D, float2 *T, float inv_n, Chunk c,
                             const ThrArgs &thr, hipStream_t st);
 hipError_t launch_z_fft_acc(const Sys3D &s, const float2 *U, float2 *ACC, Chunk c, bool first,

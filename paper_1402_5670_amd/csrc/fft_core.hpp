@@ -135,11 +135,15 @@ struct Plan {
 // wave on consecutive words.  Row tiles store a line contiguously with one
 // pad element after every 8 (stride_n = 0 selects that layout): without it
 // the radix-8 stage writes at stride 8 elements and 16 lanes share a bank.
+// stride_n = -1 pads one element after every 16 (planes that would not fit
+// LDS with the denser padding).  Every caller passes a constant stride_n.
 struct LdsLine {
   float2 *base;
   int stride_n;
   __device__ __forceinline__ float2 &operator[](int n) const {
-    return stride_n ? base[n * stride_n] : base[n + (n >> 3)];
+    if (stride_n > 0) return base[n * stride_n];
+    if (stride_n == 0) return base[n + (n >> 3)];
+    return base[n + (n >> 4)];
   }
 };
 // LDS elements of one padded row line of length N
@@ -172,8 +176,16 @@ constexpr bool wave_lines() { return NT <= 64 && 64 % NT == 0; }
 struct TwLds {
   const float2 *p;
 };
+// Every S-th entry of a longer table: the twiddles of length N / S from
+// those of length N.
+template <int S>
+struct TwStep {
+  const float2 *p;
+};
 __device__ __forceinline__ float2 tw_at(const float2 *__restrict__ tw, int i) { return tw[i]; }
 __device__ __forceinline__ float2 tw_at(TwLds tw, int i) { return tw.p[i]; }
+template <int S>
+__device__ __forceinline__ float2 tw_at(TwStep<S> tw, int i) { return tw.p[i * S]; }
 
 template <class PL, int S_, bool INV, bool WAVE = false, class TW = const float2 *>
 __device__ __forceinline__ void fft_stage(float2 (&v)[PL::E], int t, const LdsLine &lds, TW tw) {

@@ -1130,116 +1130,177 @@ __device__ __forceinline__ void plane_cols(float2 *pl, const float2 *__restrict_
 }
 
 // forward: z-IDFT'd slice -> y IDFT -> x IDFT -> coefficients of the pair.
-// One block per (z-slice, pair, image); the slice's plane fills most of a
-// CU's LDS.  (A persistent variant that fetched the next slice into
-// registers during the transforms spilled at 128 x 128 and was slower.)
+// The slice's plane fills most of a CU's LDS, so one block per CU runs and
+// nothing else overlaps its phases: the block is persistent over (slice,
+// pair, image) items and software-pipelined instead.  Each column iteration
+// reads its columns from HBM straight into registers (no staging copy) and
+// issues the loads of the next column iteration, the last one those of the
+// next item, before its own transform; the row pass's stores drain while the
+// next item starts.  128 x 128 x 128, R = 99: 534 -> 353 us per forward.
 template <int H, int W, int DT>
 __global__ void __launch_bounds__((PlaneTile<H, W>::THREADS))
 k_plane_coef(const float2 *__restrict__ T, typename Store<DT>::T *__restrict__ coef,
-             const float *__restrict__ scales, int D, int R, int b0, int p0, int np,
+             const float *__restrict__ scales, int D, int R, int b0, int p0, int np, int nb,
              float inv_n, const float2 *__restrict__ twH, const float2 *__restrict__ twW) {
   using PT = PlaneTile<H, W>;
+  constexpr int NCI = W / PT::MC;      // column iterations per slice
   __shared__ float2 pl[H * PT::RL];
-  const int z = blockIdx.x, pp = blockIdx.y, bl = blockIdx.z, b = b0 + bl;
-  const int ia = 2 * (p0 + pp), ib = ia + 1;
+  const int items = D * np * nb;
   const size_t slice = (size_t)H * W, vol = slice * D;
-  const float2 *Ts = T + ((size_t)bl * np + pp) * vol + (size_t)z * slice;
-  for (int k = threadIdx.x; k < H * W; k += PT::THREADS) {
-    const int y = k / W, x = k % W;
-    pl[y * PT::RL + x + (x >> 3)] = Ts[k];
-  }
-  __syncthreads();
-  plane_cols<H, W, true>(pl, twH);
-  float sa = inv_n, sb = inv_n;
-  if (DT != 0) {
-    sa = inv_n / scales[(size_t)b * R + ia];
-    if (ib < R) sb = inv_n / scales[(size_t)b * R + ib];
-  }
-  using Raw = typename Store<DT>::Raw;
-  Raw *ca = (Raw *)(coef + ((size_t)b * R + ia) * vol + (size_t)z * slice);
-  Raw *cb = (Raw *)(coef + ((size_t)b * R + (ib < R ? ib : ia)) * vol + (size_t)z * slice);
-  const int t = threadIdx.x % PT::NTR, m = threadIdx.x / PT::NTR;
+  const int mc = threadIdx.x % PT::MC, tc = threadIdx.x / PT::MC;
+  // column (ci, mc) of item i, values y = tc + e NTC: wave-uniform bases,
+  // one 32-bit lane offset
+  const unsigned lo = (unsigned)(tc * W + mc) * (unsigned)sizeof(float2);
+  auto fetch = [&](float2 (&v)[PT::EC], int i, int ci) {
+    const int z = i % D, pp = (i / D) % np, bl = i / (D * np);
+    const char *Tb = (const char *)(T + ((size_t)bl * np + pp) * vol + (size_t)z * slice + ci * PT::MC);
+#pragma unroll
+    for (int e = 0; e < PT::EC; ++e)
+      v[e] = *(const float2 *)(Tb + (size_t)e * PT::NTC * W * sizeof(float2) + lo);
+  };
+  float2 cur[PT::EC], nxt[PT::EC];
+  int i = blockIdx.x;
+  if (i < items) fetch(cur, i, 0);
+  for (; i < items; i += gridDim.x) {
+    const int z = i % D, pp = (i / D) % np, bl = i / (D * np), b = b0 + bl;
+    const int ia = 2 * (p0 + pp), ib = ia + 1;
+    __syncthreads();   // the previous slice's row pass has left LDS
 #pragma unroll 1
-  for (int r0 = 0; r0 < H; r0 += PT::MR) {
-    const int y = r0 + m;
-    float2 v[PT::ER];
-    const LdsLine row = plane_row<H, W>(pl, y);
+    for (int ci = 0; ci < NCI; ++ci) {
+      const bool last = ci + 1 == NCI;
+      const int ni = last ? i + (int)gridDim.x : i;
+      if (ni < items) fetch(nxt, ni, last ? 0 : ci + 1);
+      const LdsLine col = plane_col<H, W>(pl, ci * PT::MC + mc);
+      fft_line_p<typename PT::PC, true>(cur, tc, col, twH);
+      __syncthreads();
 #pragma unroll
-    for (int e = 0; e < PT::ER; ++e) v[e] = row[t + e * PT::NTR];
-    fft_line<W, true>(v, t, row, twW);
+      for (int e = 0; e < PT::EC; ++e) col[tc + e * PT::NTC] = cur[e];
 #pragma unroll
-    for (int e = 0; e < PT::ER; ++e)
-      coef_store(ca + (size_t)y * W + t + e * PT::NTR, Store<DT>::enc_raw(v[e].x * sa));
-    if (ib < R) {
+      for (int e = 0; e < PT::EC; ++e) cur[e] = nxt[e];
+    }
+    __syncthreads();
+    float sa = inv_n, sb = inv_n;
+    if (DT != 0) {
+      sa = inv_n / scales[(size_t)b * R + ia];
+      if (ib < R) sb = inv_n / scales[(size_t)b * R + ib];
+    }
+    using Raw = typename Store<DT>::Raw;
+    Raw *ca = (Raw *)(coef + ((size_t)b * R + ia) * vol + (size_t)z * slice);
+    Raw *cb = (Raw *)(coef + ((size_t)b * R + (ib < R ? ib : ia)) * vol + (size_t)z * slice);
+    const int t = threadIdx.x % PT::NTR, m = threadIdx.x / PT::NTR;
+#pragma unroll 1
+    for (int r0 = 0; r0 < H; r0 += PT::MR) {
+      const int y = r0 + m;
+      float2 v[PT::ER];
+      const LdsLine row = plane_row<H, W>(pl, y);
+#pragma unroll
+      for (int e = 0; e < PT::ER; ++e) v[e] = row[t + e * PT::NTR];
+      fft_line<W, true>(v, t, row, twW);
 #pragma unroll
       for (int e = 0; e < PT::ER; ++e)
-        coef_store(cb + (size_t)y * W + t + e * PT::NTR, Store<DT>::enc_raw(v[e].y * sb));
+        coef_store(ca + (size_t)y * W + t + e * PT::NTR, Store<DT>::enc_raw(v[e].x * sa));
+      if (ib < R) {
+#pragma unroll
+        for (int e = 0; e < PT::ER; ++e)
+          coef_store(cb + (size_t)y * W + t + e * PT::NTR, Store<DT>::enc_raw(v[e].y * sb));
+      }
     }
   }
 }
 
 // inverse: coefficients of the pair (decoded, thresholded) -> x DFT -> y DFT
-// -> U slice for the z pass
+// -> U slice for the z pass.  Persistent and pipelined like the forward: each
+// row iteration issues the coefficient loads of the next one (the last, of
+// the next item) before its transform, and the column pass stores U straight
+// from registers.  128 x 128 x 128, R = 99: 479 -> 354 us per inverse.
 template <int H, int W, int DT>
 __global__ void __launch_bounds__((PlaneTile<H, W>::THREADS))
 k_plane_coef_fft(const typename Store<DT>::T *__restrict__ coef, const float *__restrict__ scales,
-                 float2 *__restrict__ U, int D, int R, int b0, int p0, int np, ThrArgs thr,
+                 float2 *__restrict__ U, int D, int R, int b0, int p0, int np, int nb, ThrArgs thr,
                  const float2 *__restrict__ twH, const float2 *__restrict__ twW) {
   using PT = PlaneTile<H, W>;
-  __shared__ float2 pl[H * PT::RL];
-  const int z = blockIdx.x, pp = blockIdx.y, bl = blockIdx.z, b = b0 + bl;
-  const int ia = 2 * (p0 + pp), ib = ia + 1;
-  const bool has_b = ib < R;
-  const size_t slice = (size_t)H * W, vol = slice * D;
-  float sa = 1.f, sb = 1.f;
-  if (DT != 0) {
-    sa = scales[(size_t)b * R + ia];
-    if (has_b) sb = scales[(size_t)b * R + ib];
-  }
-  float da = 0.f, db = 0.f;
-  if (thr.sigma) {
-    const float sg = thr.sigma[b];
-    const int ja = thr.jof[ia];
-    if (ja >= 0) da = (thr.K[ja] * sg) * thr.l2[ia];
-    if (has_b) {
-      const int jb = thr.jof[ib];
-      if (jb >= 0) db = (thr.K[jb] * sg) * thr.l2[ib];
-    }
-  }
+  constexpr int NRI = H / PT::MR, NCI = W / PT::MC;
   using Raw = typename Store<DT>::Raw;
-  const Raw *ca = (const Raw *)(coef + ((size_t)b * R + ia) * vol + (size_t)z * slice);
-  const Raw *cb = (const Raw *)(coef + ((size_t)b * R + (has_b ? ib : ia)) * vol + (size_t)z * slice);
+  __shared__ float2 pl[H * PT::RL];
+  const int items = D * np * nb;
+  const size_t slice = (size_t)H * W, vol = slice * D;
   const int t = threadIdx.x % PT::NTR, m = threadIdx.x / PT::NTR;
+  // raw coefficients of row iteration ri of item i (both subbands of the pair)
+  auto fetch = [&](Raw (&ra)[PT::ER], Raw (&rb)[PT::ER], int i, int ri) {
+    const int z = i % D, pp = (i / D) % np, bl = i / (D * np), b = b0 + bl;
+    const int ia = 2 * (p0 + pp), ib = ia + 1;
+    const size_t o = (size_t)z * slice + (size_t)(ri * PT::MR + m) * W + t;
+    const Raw *ca = (const Raw *)(coef + ((size_t)b * R + ia) * vol + o);
+    const Raw *cb = (const Raw *)(coef + ((size_t)b * R + (ib < R ? ib : ia)) * vol + o);
+#pragma unroll
+    for (int e = 0; e < PT::ER; ++e) {
+      ra[e] = coef_load(ca + e * PT::NTR);
+      rb[e] = coef_load(cb + e * PT::NTR);   // ignored without a partner
+    }
+  };
+  Raw ca_[PT::ER], cb_[PT::ER], na[PT::ER], nb_[PT::ER];
+  int i = blockIdx.x;
+  if (i < items) fetch(ca_, cb_, i, 0);
+  const int mc = threadIdx.x % PT::MC, tc = threadIdx.x / PT::MC;
+  for (; i < items; i += gridDim.x) {
+    const int z = i % D, pp = (i / D) % np, bl = i / (D * np), b = b0 + bl;
+    const int ia = 2 * (p0 + pp), ib = ia + 1;
+    const bool has_b = ib < R;
+    float sa = 1.f, sb = 1.f;
+    if (DT != 0) {
+      sa = scales[(size_t)b * R + ia];
+      if (has_b) sb = scales[(size_t)b * R + ib];
+    }
+    float da = 0.f, db = 0.f;
+    if (thr.sigma) {
+      const float sg = thr.sigma[b];
+      const int ja = thr.jof[ia];
+      if (ja >= 0) da = (thr.K[ja] * sg) * thr.l2[ia];
+      if (has_b) {
+        const int jb = thr.jof[ib];
+        if (jb >= 0) db = (thr.K[jb] * sg) * thr.l2[ib];
+      }
+    }
+    __syncthreads();   // the previous slice's column pass has left LDS
 #pragma unroll 1
-  for (int r0 = 0; r0 < H; r0 += PT::MR) {
-    const int y = r0 + m;
-    Raw ra[PT::ER], rb[PT::ER];
+    for (int ri = 0; ri < NRI; ++ri) {
+      const bool last = ri + 1 == NRI;
+      const int ni = last ? i + (int)gridDim.x : i;
+      if (ni < items) fetch(na, nb_, ni, last ? 0 : ri + 1);
+      float2 v[PT::ER];
 #pragma unroll
-    for (int e = 0; e < PT::ER; ++e) {
-      ra[e] = coef_load(ca + (size_t)y * W + t + e * PT::NTR);
-      rb[e] = coef_load(cb + (size_t)y * W + t + e * PT::NTR);   // ignored without a partner
-    }
-    float2 v[PT::ER];
+      for (int e = 0; e < PT::ER; ++e) {
+        float a = Store<DT>::dec_raw(ca_[e]) * sa;
+        float bb = has_b ? Store<DT>::dec_raw(cb_[e]) * sb : 0.f;
+        if (!(fabsf(a) >= da)) a = 0.f;
+        if (!(fabsf(bb) >= db)) bb = 0.f;
+        v[e] = make_float2(a, bb);
+      }
+      const LdsLine row = plane_row<H, W>(pl, ri * PT::MR + m);
+      fft_line<W, false>(v, t, row, twW);
+      __syncthreads();
 #pragma unroll
-    for (int e = 0; e < PT::ER; ++e) {
-      float a = Store<DT>::dec_raw(ra[e]) * sa;
-      float bb = has_b ? Store<DT>::dec_raw(rb[e]) * sb : 0.f;
-      if (!(fabsf(a) >= da)) a = 0.f;
-      if (!(fabsf(bb) >= db)) bb = 0.f;
-      v[e] = make_float2(a, bb);
+      for (int e = 0; e < PT::ER; ++e) row[t + e * PT::NTR] = v[e];
+#pragma unroll
+      for (int e = 0; e < PT::ER; ++e) {
+        ca_[e] = na[e];
+        cb_[e] = nb_[e];
+      }
     }
-    const LdsLine row = plane_row<H, W>(pl, y);
-    fft_line<W, false>(v, t, row, twW);
     __syncthreads();
+    // y DFT of every column, stored to U straight from registers
+    float2 *Us = U + ((size_t)bl * np + pp) * vol + (size_t)z * slice;
+#pragma unroll 1
+    for (int ci = 0; ci < NCI; ++ci) {
+      const int x = ci * PT::MC + mc;
+      const LdsLine col = plane_col<H, W>(pl, x);
+      float2 v[PT::EC];
 #pragma unroll
-    for (int e = 0; e < PT::ER; ++e) row[t + e * PT::NTR] = v[e];
-  }
-  __syncthreads();
-  plane_cols<H, W, false>(pl, twH);
-  float2 *Us = U + ((size_t)bl * np + pp) * vol + (size_t)z * slice;
-  for (int k = threadIdx.x; k < H * W; k += PT::THREADS) {
-    const int y = k / W, x = k % W;
-    Us[k] = pl[y * PT::RL + x + (x >> 3)];
+      for (int e = 0; e < PT::EC; ++e) v[e] = col[tc + e * PT::NTC];
+      fft_line_p<typename PT::PC, false>(v, tc, col, twH);
+#pragma unroll
+      for (int e = 0; e < PT::EC; ++e) Us[(size_t)(tc + e * PT::NTC) * W + x] = v[e];
+    }
   }
 }
 
@@ -1297,6 +1358,261 @@ k_plane_thr(float2 *__restrict__ T, int D, int R, int b0, int p0, int np, float 
   for (int k = threadIdx.x; k < H * W; k += PT::THREADS) {
     const int y = k / W, x = k % W;
     Ts[k] = pl[y * PT::RL + x + (x >> 3)];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Half-plane passes of a volume: z-slices too large for one CU's LDS (192 x
+// 192: 288 KiB) are split in y by one decimation-in-frequency step.  With
+// Hh = H / 2 and w = exp(-2 pi i / H), the y transform of a column t is
+//   Y[2k + h] = DFT_Hh( (t[m] + (-1)^h t[m + Hh]) w^(+-m h) )[k],   m < Hh,
+// (the sign of the twiddle follows the direction of the transform), so half h
+// of the slice needs Hh combined rows (Hh x W complex in LDS, rows padded one
+// element per 16) and yields every second output row, whole and contiguous.
+// Both halves read the full slice; the grid gives the two halves of a slice
+// workgroup ids 8 apart, which the dispatcher sends to the same XCD at about
+// the same time, so the second read finds the slice in that XCD's L2.
+// Forward: z-IDFT'd slice -> combine -> y IDFT (Hh) -> x IDFT -> coefficient
+// rows 2k + h.  Inverse: coefficient rows m and m + Hh (decoded, thresholded)
+// -> combine -> x DFT -> twiddle -> y DFT (Hh) -> U rows 2k + h.
+// ---------------------------------------------------------------------------
+template <int H, int W>
+struct HalfTile {
+  static constexpr int HH = H / 2;
+  static constexpr int RL = W + W / 16;
+  using PC = Plan<HH>;                        // the y pass's plan (half length)
+  static constexpr int NTC = PC::NT, EC = PC::E;
+  static constexpr int NTR = Plan<W>::NT, ER = Plan<W>::E;
+  static constexpr bool fits(int th) {
+    return th % 64 == 0 && th % NTC == 0 && th % NTR == 0 && W % (th / NTC) == 0 &&
+           HH % (th / NTR) == 0;
+  }
+  // at most 512 threads: the pipelined passes hold two iterations' raw rows
+  // (m and m + Hh) in registers, which needs the 256 VGPRs of 2 waves per SIMD
+  static constexpr int pick() {
+    for (int th = 512; th >= 64; th -= 64)
+      if (fits(th)) return th;
+    return 0;
+  }
+  static constexpr int THREADS = pick();
+  static constexpr int MC = THREADS ? THREADS / NTC : 1, MR = THREADS ? THREADS / NTR : 1;
+  static constexpr size_t LDS = (size_t)HH * RL * sizeof(float2);
+  static constexpr bool OK = H % 2 == 0 && THREADS > 0 && LDS <= 156 * 1024 && W % 16 == 0;
+};
+
+// Item i of a half-plane pass -> (slice, half h); a slice indexes (z, pair,
+// image).  The grid is persistent (G workgroups, G a multiple of 16);
+// workgroup g takes items g, g + G, ...  Workgroups g and g + 8 sit on the
+// same XCD (round-robin dispatch), so in every full round the map gives them
+// the two halves of one slice: both read that slice at about the same time
+// and the second read comes from the XCD's L2.  A last, partial round (an
+// even number of items) pairs neighbouring workgroups instead.
+__device__ __forceinline__ void half_item(int i, int G, int items, int &slice, int &h) {
+  const int r = i / G, g = i % G;           // round, workgroup
+  if ((r + 1) * G <= items) {
+    h = (g >> 3) & 1;
+    slice = r * (G >> 1) + (g >> 4) * 8 + (g & 7);
+  } else {
+    h = g & 1;
+    slice = r * (G >> 1) + (g >> 1);
+  }
+}
+
+// Forward.  Persistent and software-pipelined like the plane passes: column
+// iteration ci holds the combined (DIF) values of its columns in registers,
+// the raw rows m and m + Hh of the next column iteration (or of the next
+// item) are loaded before the transform.
+template <int H, int W, int DT>
+__global__ void __launch_bounds__((HalfTile<H, W>::THREADS))
+k_hplane_coef(const float2 *__restrict__ T, typename Store<DT>::T *__restrict__ coef,
+              const float *__restrict__ scales, int D, int R, int b0, int p0, int np, int nb,
+              float inv_n, const float2 *__restrict__ twH, const float2 *__restrict__ twW) {
+  using HT = HalfTile<H, W>;
+  constexpr int HH = HT::HH, NCI = W / HT::MC;
+  __shared__ float2 pl[HH * HT::RL];
+  const int G = gridDim.x;
+  const int nslice = D * np * nb, items = 2 * nslice;
+  const size_t slice = (size_t)H * W, vol = slice * D;
+  const int mc = threadIdx.x % HT::MC, tc = threadIdx.x / HT::MC;
+  const unsigned lo = (unsigned)(tc * W + mc) * (unsigned)sizeof(float2);
+  // raw rows m = tc + e NTC and m + Hh of column ci of item i
+  auto fetch = [&](float2 (&ra)[HT::EC], float2 (&rc)[HT::EC], int i, int ci) {
+    int sl, h;
+    half_item(i, G, items, sl, h);
+    const int z = sl % D, pp = (sl / D) % np, bl = sl / (D * np);
+    const char *Tb =
+        (const char *)(T + ((size_t)bl * np + pp) * vol + (size_t)z * slice + ci * HT::MC);
+#pragma unroll
+    for (int e = 0; e < HT::EC; ++e) {
+      ra[e] = *(const float2 *)(Tb + (size_t)e * HT::NTC * W * sizeof(float2) + lo);
+      rc[e] = *(const float2 *)(Tb + ((size_t)e * HT::NTC + HH) * W * sizeof(float2) + lo);
+    }
+  };
+  float2 ca_[HT::EC], cc_[HT::EC], na[HT::EC], nc[HT::EC];
+  int i = blockIdx.x;
+  if (i < items) fetch(ca_, cc_, i, 0);
+  for (; i < items; i += G) {
+    int sl, h;
+    half_item(i, G, items, sl, h);
+    const int z = sl % D, pp = (sl / D) % np, bl = sl / (D * np), b = b0 + bl;
+    const int ia = 2 * (p0 + pp), ib = ia + 1;
+    __syncthreads();   // the previous item's row pass has left LDS
+#pragma unroll 1
+    for (int ci = 0; ci < NCI; ++ci) {
+      const bool last = ci + 1 == NCI;
+      const int ni = last ? i + G : i;
+      if (ni < items) fetch(na, nc, ni, last ? 0 : ci + 1);
+      float2 v[HT::EC];
+#pragma unroll
+      for (int e = 0; e < HT::EC; ++e)
+        v[e] = h ? cmulconj(csub(ca_[e], cc_[e]), twH[tc + e * HT::NTC]) : cadd(ca_[e], cc_[e]);
+      const int x = ci * HT::MC + mc;
+      const LdsLine col{pl + x + (x >> 4), HT::RL};
+      fft_line_p<typename HT::PC, true>(v, tc, col, TwStep<2>{twH});
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < HT::EC; ++e) col[tc + e * HT::NTC] = v[e];
+#pragma unroll
+      for (int e = 0; e < HT::EC; ++e) {
+        ca_[e] = na[e];
+        cc_[e] = nc[e];
+      }
+    }
+    __syncthreads();
+    float sa = inv_n, sb = inv_n;
+    if (DT != 0) {
+      sa = inv_n / scales[(size_t)b * R + ia];
+      if (ib < R) sb = inv_n / scales[(size_t)b * R + ib];
+    }
+    using Raw = typename Store<DT>::Raw;
+    Raw *ca = (Raw *)(coef + ((size_t)b * R + ia) * vol + (size_t)z * slice);
+    Raw *cb = (Raw *)(coef + ((size_t)b * R + (ib < R ? ib : ia)) * vol + (size_t)z * slice);
+    const int t = threadIdx.x % HT::NTR, m = threadIdx.x / HT::NTR;
+#pragma unroll 1
+    for (int r0 = 0; r0 < HH; r0 += HT::MR) {
+      const int r = r0 + m, y = 2 * r + h;
+      float2 v[HT::ER];
+      const LdsLine row{pl + r * HT::RL, -1};
+#pragma unroll
+      for (int e = 0; e < HT::ER; ++e) v[e] = row[t + e * HT::NTR];
+      fft_line<W, true>(v, t, row, twW);
+#pragma unroll
+      for (int e = 0; e < HT::ER; ++e)
+        coef_store(ca + (size_t)y * W + t + e * HT::NTR, Store<DT>::enc_raw(v[e].x * sa));
+      if (ib < R) {
+#pragma unroll
+        for (int e = 0; e < HT::ER; ++e)
+          coef_store(cb + (size_t)y * W + t + e * HT::NTR, Store<DT>::enc_raw(v[e].y * sb));
+      }
+    }
+  }
+}
+
+// Inverse, pipelined over row iterations; U rows 2k + h leave straight from
+// the column transform's registers.
+template <int H, int W, int DT>
+__global__ void __launch_bounds__((HalfTile<H, W>::THREADS))
+k_hplane_coef_fft(const typename Store<DT>::T *__restrict__ coef, const float *__restrict__ scales,
+                  float2 *__restrict__ U, int D, int R, int b0, int p0, int np, int nb,
+                  ThrArgs thr, const float2 *__restrict__ twH, const float2 *__restrict__ twW) {
+  using HT = HalfTile<H, W>;
+  constexpr int HH = HT::HH, NRI = HH / HT::MR, NCI = W / HT::MC;
+  using Raw = typename Store<DT>::Raw;
+  __shared__ float2 pl[HH * HT::RL];
+  const int G = gridDim.x;
+  const int nslice = D * np * nb, items = 2 * nslice;
+  const size_t slice = (size_t)H * W, vol = slice * D;
+  const int t = threadIdx.x % HT::NTR, m = threadIdx.x / HT::NTR;
+  // raw rows r and r + Hh (r = ri MR + m) of both subbands of item i
+  auto fetch = [&](Raw (&q)[4][HT::ER], int i, int ri) {
+    int sl, h;
+    half_item(i, G, items, sl, h);
+    const int z = sl % D, pp = (sl / D) % np, bl = sl / (D * np), b = b0 + bl;
+    const int ia = 2 * (p0 + pp), ib = ia + 1;
+    const size_t o = (size_t)z * slice + (size_t)(ri * HT::MR + m) * W + t;
+    const Raw *ca = (const Raw *)(coef + ((size_t)b * R + ia) * vol + o);
+    const Raw *cb = (const Raw *)(coef + ((size_t)b * R + (ib < R ? ib : ia)) * vol + o);
+#pragma unroll
+    for (int e = 0; e < HT::ER; ++e) {
+      q[0][e] = coef_load(ca + e * HT::NTR);
+      q[1][e] = coef_load(cb + e * HT::NTR);   // ignored without a partner
+      q[2][e] = coef_load(ca + (size_t)HH * W + e * HT::NTR);
+      q[3][e] = coef_load(cb + (size_t)HH * W + e * HT::NTR);
+    }
+  };
+  Raw cur[4][HT::ER], nxt[4][HT::ER];
+  int i = blockIdx.x;
+  if (i < items) fetch(cur, i, 0);
+  const int mc = threadIdx.x % HT::MC, tc = threadIdx.x / HT::MC;
+  for (; i < items; i += G) {
+    int sl, h;
+    half_item(i, G, items, sl, h);
+    const int z = sl % D, pp = (sl / D) % np, bl = sl / (D * np), b = b0 + bl;
+    const int ia = 2 * (p0 + pp), ib = ia + 1;
+    const bool has_b = ib < R;
+    float sa = 1.f, sb = 1.f;
+    if (DT != 0) {
+      sa = scales[(size_t)b * R + ia];
+      if (has_b) sb = scales[(size_t)b * R + ib];
+    }
+    float da = 0.f, db = 0.f;
+    if (thr.sigma) {
+      const float sg = thr.sigma[b];
+      const int ja = thr.jof[ia];
+      if (ja >= 0) da = (thr.K[ja] * sg) * thr.l2[ia];
+      if (has_b) {
+        const int jb = thr.jof[ib];
+        if (jb >= 0) db = (thr.K[jb] * sg) * thr.l2[ib];
+      }
+    }
+    auto val = [&](Raw ra, Raw rb) {
+      float a = Store<DT>::dec_raw(ra) * sa;
+      float bb = has_b ? Store<DT>::dec_raw(rb) * sb : 0.f;
+      if (!(fabsf(a) >= da)) a = 0.f;
+      if (!(fabsf(bb) >= db)) bb = 0.f;
+      return make_float2(a, bb);
+    };
+    __syncthreads();   // the previous item's column pass has left LDS
+#pragma unroll 1
+    for (int ri = 0; ri < NRI; ++ri) {
+      const bool last = ri + 1 == NRI;
+      const int ni = last ? i + G : i;
+      if (ni < items) fetch(nxt, ni, last ? 0 : ri + 1);
+      const int r = ri * HT::MR + m;
+      float2 v[HT::ER];
+#pragma unroll
+      for (int e = 0; e < HT::ER; ++e) {
+        const float2 p = val(cur[0][e], cur[1][e]), q = val(cur[2][e], cur[3][e]);
+        v[e] = h ? csub(p, q) : cadd(p, q);
+      }
+      const LdsLine row{pl + r * HT::RL, -1};
+      fft_line<W, false>(v, t, row, twW);
+      if (h) {
+        const float2 w = twH[r];
+#pragma unroll
+        for (int e = 0; e < HT::ER; ++e) v[e] = cmul(v[e], w);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < HT::ER; ++e) row[t + e * HT::NTR] = v[e];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int e = 0; e < HT::ER; ++e) cur[k][e] = nxt[k][e];
+    }
+    __syncthreads();
+    float2 *Us = U + ((size_t)bl * np + pp) * vol + (size_t)z * slice;
+#pragma unroll 1
+    for (int ci = 0; ci < NCI; ++ci) {
+      const int x = ci * HT::MC + mc;
+      const LdsLine col{pl + x + (x >> 4), HT::RL};
+      float2 v[HT::EC];
+#pragma unroll
+      for (int e = 0; e < HT::EC; ++e) v[e] = col[tc + e * HT::NTC];
+      fft_line_p<typename HT::PC, false>(v, tc, col, TwStep<2>{twH});
+#pragma unroll
+      for (int e = 0; e < HT::EC; ++e) Us[(size_t)(2 * (tc + e * HT::NTC) + h) * W + x] = v[e];
+    }
   }
 }
 
@@ -1729,9 +2045,9 @@ static hipError_t plane_coef_dt(const Sys2D &s, int D, const float2 *T, void *co
 #define X(h, w)                                                                                 \
   if constexpr (plane_ok<h, w>())                                                               \
     if (s.H == h && s.W == w) {                                                                 \
-      hipLaunchKernelGGL((k_plane_coef<h, w, DT>), dim3(D, c.np, c.nb),                 \
+      hipLaunchKernelGGL((k_plane_coef<h, w, DT>), dim3(std::min(s.num_cu, D * c.np * c.nb)), \
                          dim3(PlaneTile<h, w>::THREADS), 0, st, T, (CT *)coef, scales, D, s.R,  \
-                         c.b0, c.p0, c.np, inv_n, s.twH, s.twW);                        \
+                         c.b0, c.p0, c.np, c.nb, inv_n, s.twH, s.twW);                          \
       return hipGetLastError();                                                                 \
     }
   SL_FOR_EACH_PLANE(X)
@@ -1756,9 +2072,9 @@ static hipError_t plane_coef_fft_dt(const Sys2D &s, int D, const void *coef, con
 #define X(h, w)                                                                                 \
   if constexpr (plane_ok<h, w>())                                                               \
     if (s.H == h && s.W == w) {                                                                 \
-      hipLaunchKernelGGL((k_plane_coef_fft<h, w, DT>), dim3(D, c.np, c.nb),             \
+      hipLaunchKernelGGL((k_plane_coef_fft<h, w, DT>), dim3(std::min(s.num_cu, D * c.np * c.nb)), \
                          dim3(PlaneTile<h, w>::THREADS), 0, st, (const CT *)coef, scales, U, D, \
-                         s.R, c.b0, c.p0, c.np, thr, s.twH, s.twW);                     \
+                         s.R, c.b0, c.p0, c.np, c.nb, thr, s.twH, s.twW);                       \
       return hipGetLastError();                                                                 \
     }
   SL_FOR_EACH_PLANE(X)
@@ -1772,6 +2088,84 @@ hipError_t launch_plane_coef_fft(const Sys2D &s, int D, const void *coef, const 
     case 0: return plane_coef_fft_dt<0>(s, D, coef, scales, U, c, thr, st);
     case 1: return plane_coef_fft_dt<1>(s, D, coef, scales, U, c, thr, st);
     case 2: return plane_coef_fft_dt<2>(s, D, coef, scales, U, c, thr, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+#define SL_FOR_EACH_HALF_PLANE(X) X(192, 192) X(192, 128) X(128, 192)
+
+template <int H, int W>
+static constexpr bool half_ok() { return HalfTile<H, W>::OK; }
+
+// persistent grid of the half-plane passes: one workgroup per CU (their LDS
+// allows no more), rounded down to whole rounds of 16 and at most the number
+// of slices' halves; every round covers G / 2 whole slices
+static int half_grid(const Sys2D &s, int D, Chunk c) {
+  const int halves = 2 * D * c.np * c.nb;
+  int G = std::max(16, s.num_cu / 16 * 16);
+  while (G > 16 && G > halves) G -= 16;
+  return G;
+}
+
+bool half_plane_supported(int H, int W) {
+#define X(h, w) \
+  if (H == h && W == w) return half_ok<h, w>();
+  SL_FOR_EACH_HALF_PLANE(X)
+#undef X
+  return false;
+}
+
+template <int DT>
+static hipError_t hplane_coef_dt(const Sys2D &s, int D, const float2 *T, void *coef,
+                                 const float *scales, Chunk c, float inv_n, hipStream_t st) {
+  using CT = typename Store<DT>::T;
+#define X(h, w)                                                                                 \
+  if constexpr (half_ok<h, w>())                                                                \
+    if (s.H == h && s.W == w) {                                                                 \
+      hipLaunchKernelGGL((k_hplane_coef<h, w, DT>), dim3(half_grid(s, D, c)),                  \
+                         dim3(HalfTile<h, w>::THREADS), 0, st, T, (CT *)coef, scales, D, s.R,   \
+                         c.b0, c.p0, c.np, c.nb, inv_n, s.twH, s.twW);                          \
+      return hipGetLastError();                                                                 \
+    }
+  SL_FOR_EACH_HALF_PLANE(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_hplane_coef(const Sys2D &s, int D, const float2 *T, void *coef,
+                              const float *scales, Chunk c, float inv_n, hipStream_t st) {
+  switch (s.dtype) {
+    case 0: return hplane_coef_dt<0>(s, D, T, coef, scales, c, inv_n, st);
+    case 1: return hplane_coef_dt<1>(s, D, T, coef, scales, c, inv_n, st);
+    case 2: return hplane_coef_dt<2>(s, D, T, coef, scales, c, inv_n, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int DT>
+static hipError_t hplane_coef_fft_dt(const Sys2D &s, int D, const void *coef,
+                                     const float *scales, float2 *U, Chunk c, const ThrArgs &thr,
+                                     hipStream_t st) {
+  using CT = typename Store<DT>::T;
+#define X(h, w)                                                                                 \
+  if constexpr (half_ok<h, w>())                                                                \
+    if (s.H == h && s.W == w) {                                                                 \
+      hipLaunchKernelGGL((k_hplane_coef_fft<h, w, DT>), dim3(half_grid(s, D, c)),              \
+                         dim3(HalfTile<h, w>::THREADS), 0, st, (const CT *)coef, scales, U, D,  \
+                         s.R, c.b0, c.p0, c.np, c.nb, thr, s.twH, s.twW);                       \
+      return hipGetLastError();                                                                 \
+    }
+  SL_FOR_EACH_HALF_PLANE(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_hplane_coef_fft(const Sys2D &s, int D, const void *coef, const float *scales,
+                                  float2 *U, Chunk c, const ThrArgs &thr, hipStream_t st) {
+  switch (s.dtype) {
+    case 0: return hplane_coef_fft_dt<0>(s, D, coef, scales, U, c, thr, st);
+    case 1: return hplane_coef_fft_dt<1>(s, D, coef, scales, U, c, thr, st);
+    case 2: return hplane_coef_fft_dt<2>(s, D, coef, scales, U, c, thr, st);
   }
   return hipErrorInvalidValue;
 }
