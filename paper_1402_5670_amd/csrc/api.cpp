@@ -167,6 +167,7 @@ sl::Sys3D view3d(const sl_system *s) {
   v.W = (int)s->cfg.dims[2];
   v.R = s->R;
   v.dtype = s->cfg.dtype;
+  v.num_cu = s->num_cu;
   v.pairs = s->d_zpairs;
   v.tab = s->d_ztab;
   v.psi = s->d_psi;

@@ -153,6 +153,7 @@ struct ZPair {
 
 struct Sys3D {
   int D, H, W, R, dtype;
+  int num_cu;                 // compute units of the device (grid sizing)
   const ZPair *pairs;         // [(R + 1) / 2]
   const float2 *tab;          // per-pair factor blocks
   const float *psi;           // [D][H][W] Psi_hat

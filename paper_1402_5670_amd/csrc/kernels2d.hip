@@ -1262,7 +1262,7 @@ k_plane_coef_fft(const typename Store<DT>::T *__restrict__ coef, const float *__
       }
     }
     __syncthreads();   // the previous slice's column pass has left LDS
-#pragma unroll 1
+#pragma unroll
     for (int ri = 0; ri < NRI; ++ri) {
       const bool last = ri + 1 == NRI;
       const int ni = last ? i + (int)gridDim.x : i;

@@ -78,7 +78,7 @@ template <int N>
 __global__ void __launch_bounds__(Tile3<N>::THREADS)
 k_z_filter_ifft(const float2 *__restrict__ F, const ZPair *__restrict__ pairs,
                 const float2 *__restrict__ tab, float2 *__restrict__ T, int H, int W, int R,
-                int b0, int p0, int np, const float2 *__restrict__ tw) {
+                int b0, int p0, int np, int split, const float2 *__restrict__ tw) {
   constexpr int NT = Tile3<N>::NT, M = Tile3<N>::M, E = Tile3<N>::E;
   __shared__ float2 lds[M * N];
   __shared__ float2 twl[N];   // twiddles staged once (ordered by the FFT's leading barrier)
@@ -89,15 +89,19 @@ k_z_filter_ifft(const float2 *__restrict__ F, const ZPair *__restrict__ pairs,
   const bool ok = col < HW;
   const int cc = ok ? col : 0;
   const int y = cc / W, x = cc % W;
-  const int b = b0 + blockIdx.y;
+  // blockIdx.y = (image of the chunk, part of the pair loop)
+  const int bl = blockIdx.y / split, part = blockIdx.y % split;
+  const int per = (np + split - 1) / split;
+  const int q0 = part * per, q1 = min(np, q0 + per);
+  const int b = b0 + bl;
   const size_t vol = (size_t)N * HW;
   float2 f[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) f[e] = F[(size_t)b * vol + (size_t)(t + e * NT) * HW + cc];
-  float2 cn = (tab + pairs[p0].c)[y * W + x];
-  for (int pp = 0; pp < np; ++pp) {
+  float2 cn = q0 < q1 ? (tab + pairs[p0 + q0].c)[y * W + x] : make_float2(0.f, 0.f);
+  for (int pp = q0; pp < q1; ++pp) {
     const float2 c = cn;
-    if (pp + 1 < np) cn = (tab + pairs[p0 + pp + 1].c)[y * W + x];
+    if (pp + 1 < q1) cn = (tab + pairs[p0 + pp + 1].c)[y * W + x];
     float2 v[E];
     with_zfilters<NT>(tab, pairs[p0 + pp], c, t, y, x, H, W, [&](const auto &psi) {
 #pragma unroll
@@ -108,7 +112,7 @@ k_z_filter_ifft(const float2 *__restrict__ F, const ZPair *__restrict__ pairs,
     });
     fft_line_p<Plan<N>, true>(v, t, LdsLine{lds + m, M}, TwLds{twl});
     if (ok) {
-      float2 *To = T + ((size_t)blockIdx.y * np + pp) * vol + col;
+      float2 *To = T + ((size_t)bl * np + pp) * vol + col;
 #pragma unroll
       for (int e = 0; e < E; ++e) stream_store(&To[(size_t)(t + e * NT) * HW], v[e]);
     }
@@ -177,16 +181,48 @@ k_z_fft_acc(const float2 *__restrict__ U, const ZPair *__restrict__ pairs,
 #define SL_FOR_EACH_N(X) \
   X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
 
+// Parts to split the forward z pass's pair loop into.  Its blocks run the
+// whole pair loop of a chunk, so a grid a little larger than one round of
+// resident blocks leaves a mostly idle last round (192^3: 2304 blocks, 1024
+// resident, three rounds for 2.25 rounds of work).  Each part reloads its
+// column tile of F (1/np of what it writes); the split that minimises the
+// rounds per unit of work wins, ties going to fewer parts.
+template <int N>
+static int z_split(int nblocks, int np, int num_cu) {
+  static int per_cu = -1;
+  if (per_cu < 0) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_z_filter_ifft<N>, Tile3<N>::THREADS,
+                                                     0) != hipSuccess || n < 1)
+      n = 1;
+    per_cu = n;
+  }
+  const long resident = (long)per_cu * num_cu;
+  int best = 1;
+  double best_cost = 1e30;
+  for (int sp = 1; sp <= 4 && sp <= np; ++sp) {
+    const long rounds = ((long)nblocks * sp + resident - 1) / resident;
+    const double cost = (double)rounds / sp;
+    if (cost < best_cost - 1e-9) {
+      best_cost = cost;
+      best = sp;
+    }
+  }
+  return best;
+}
+
 hipError_t launch_z_filter_ifft(const Sys3D &s, const float2 *F, float2 *T, Chunk c,
                                 hipStream_t st) {
   const int HW = s.H * s.W;
   switch (s.D) {
 #define X(N)                                                                                  \
-  case N:                                                                                     \
-    hipLaunchKernelGGL(k_z_filter_ifft<N>, dim3((HW + Tile3<N>::M - 1) / Tile3<N>::M, c.nb),   \
-                       dim3(Tile3<N>::THREADS), 0, st, F, s.pairs, s.tab, T, s.H, s.W, s.R, c.b0, \
-                       c.p0, c.np, s.twD);                                                    \
-    break;
+  case N: {                                                                                   \
+    const int tiles = (HW + Tile3<N>::M - 1) / Tile3<N>::M;                                   \
+    const int sp = z_split<N>(tiles * c.nb, c.np, s.num_cu);                                  \
+    hipLaunchKernelGGL(k_z_filter_ifft<N>, dim3(tiles, c.nb * sp), dim3(Tile3<N>::THREADS), 0, \
+                       st, F, s.pairs, s.tab, T, s.H, s.W, s.R, c.b0, c.p0, c.np, sp, s.twD); \
+    break;                                                                                    \
+  }
     SL_FOR_EACH_N(X)
 #undef X
     default:
