@@ -943,10 +943,17 @@ k_cols_fft_acc(const float2 *__restrict__ U, const float *__restrict__ filt,
   const bool ok = col < W;
   const int cc = ok ? col : 0;
   const size_t plane = (size_t)N * W;
-  // element offsets within a plane from uniform plane bases: thread (m, t)
-  // owns rows t + e NT of column cc (32-bit offsets, so that the strided
-  // addresses are not held as 64-bit registers)
-  const unsigned o0 = (unsigned)t * W + cc, se = (unsigned)NT * W;
+  // Thread (m, t) owns rows t + e NT of column cc.  Every access is a
+  // wave-uniform base (plane, row step e NT) plus one 32-bit lane byte offset
+  // (row t, column cc): no per-value addresses stay live across the pair loop.
+  const unsigned lo = ((unsigned)t * W + cc) * 8u, lo4 = lo / 2;
+  const size_t sb8 = (size_t)NT * W * 8, sb4 = sb8 / 2;
+  auto at8 = [&](const float2 *base, int e) -> const float2 * {
+    return (const float2 *)((const char *)base + e * sb8 + lo);
+  };
+  auto at4 = [&](const float *base, int e) -> const float * {
+    return (const float *)((const char *)base + e * sb4 + lo4);
+  };
   // pair group z sums pairs [q0, q1) of the chunk into its own partial sum:
   // ACC for z = 0, part[z - 1] ([Btot] planes each) otherwise; with several
   // groups k_cols_acc_finish adds the partial sums after the last chunk.  A
@@ -960,8 +967,7 @@ k_cols_fft_acc(const float2 *__restrict__ U, const float *__restrict__ filt,
     const int bl = blockIdx.y * BT + bt;
     const float2 *accp = dst + (size_t)(b0 + (bl < nb ? bl : 0)) * plane;
 #pragma unroll
-    for (int e = 0; e < E; ++e)
-      acc[bt][e] = first ? make_float2(0.f, 0.f) : accp[o0 + e * se];
+    for (int e = 0; e < E; ++e) acc[bt][e] = first ? make_float2(0.f, 0.f) : *at8(accp, e);
   }
   for (int pp = q0; pp < q1; ++pp) {
     const int ia = 2 * (p0 + pp), ib = ia + 1;
@@ -970,8 +976,8 @@ k_cols_fft_acc(const float2 *__restrict__ U, const float *__restrict__ filt,
     float a[E], bb[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      a[e] = fa[o0 + e * se];
-      bb[e] = ib < R ? fb[o0 + e * se] : 0.f;
+      a[e] = *at4(fa, e);
+      bb[e] = ib < R ? *at4(fb, e) : 0.f;
     }
 #pragma unroll
     for (int bt = 0; bt < BT; ++bt) {
@@ -979,7 +985,7 @@ k_cols_fft_acc(const float2 *__restrict__ U, const float *__restrict__ filt,
       const float2 *Ui = U + ((size_t)(bl < nb ? bl : 0) * np + pp) * plane;
       float2 v[E];
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = stream_load<SL_NT_STREAM && MW != kInvNarrow>(&Ui[o0 + e * se]);
+      for (int e = 0; e < E; ++e) v[e] = stream_load<SL_NT_STREAM && MW != kInvNarrow>(at8(Ui, e));
       fft_line_p<PL, false>(v, t, LdsLine{lds + m, M}, tw);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -995,7 +1001,7 @@ k_cols_fft_acc(const float2 *__restrict__ U, const float *__restrict__ filt,
     if (last) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const float d = psi[o0 + e * se];
+        const float d = *at4(psi, e);
         acc[bt][e] = make_float2(acc[bt][e].x / d, acc[bt][e].y / d);
       }
       fft_line_p<PL, true>(acc[bt], t, LdsLine{lds + m, M}, tw);
@@ -1003,7 +1009,7 @@ k_cols_fft_acc(const float2 *__restrict__ U, const float *__restrict__ filt,
     if (ok && bl < nb) {
       float2 *accp = dst + (size_t)(b0 + bl) * plane;
 #pragma unroll
-      for (int e = 0; e < E; ++e) accp[o0 + e * se] = acc[bt][e];
+      for (int e = 0; e < E; ++e) *(float2 *)at8(accp, e) = acc[bt][e];
     }
   }
 }
