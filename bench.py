@@ -453,6 +453,12 @@ def main():
     mt = measured_traffic(dom)
     roof.update({"kernel": dom, "avg_launch_us": round(d["avg_launch_us"], 2),
                  "launches_per_step": launches,
+                 # what 'achieved' and 'frac' count: the pass's algorithmic
+                 # bytes (or flops) per launch over its average launch time
+                 "basis": ("algorithmic: bytes the pass must move (inputs and outputs of "
+                           "the transform, coefficients once, filters once per call), not "
+                           "counter traffic" if roof["bound"] == "hbm" else
+                           "algorithmic: FFT and filter flops of the pass"),
                  # HBM bytes per launch from the copy-calibrated counters
                  # (FETCH_SIZE + WRITE_SIZE), null if the kernels changed since
                  "traffic": round(mt["bytes"]) if mt else None})
@@ -460,6 +466,9 @@ def main():
         roof.update({"traffic_unit": "bytes per launch",
                      "traffic_read_bytes": round(mt["read_bytes"]),
                      "traffic_write_bytes": round(mt["write_bytes"]),
+                     # the counted bytes over the same launch time
+                     "traffic_GBps": round(mt["bytes"] / (d["avg_launch_us"] * 1e3), 1),
+                     "traffic_frac": round(mt["bytes"] / (d["avg_launch_us"] * 1e3) / HBM_PEAK_GBS, 4),
                      "traffic_kernel": mt["kernel"]})
 
     step_bytes = sum(pass_work(n, 0, H, W, R, Bn)[0] for n in rep)
