@@ -175,10 +175,12 @@ def psnr(ref, est):
     return float(20.0 * np.log10(np.sqrt(np.size(ref)) / err))
 
 
-def time_call(fn, reps):
-    """Mean milliseconds of fn() over reps calls (device events, one warm-up)."""
+def time_call(fn, reps, warmup=1):
+    """Mean milliseconds of fn() over reps calls (device events, after warmup
+    untimed calls)."""
     import torch
-    fn()
+    for _ in range(warmup):
+        fn()
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record()
@@ -223,8 +225,11 @@ def other_configs(reps=10):
     c3, _ = s3.alloc_coeffs(1, dev)
     o3 = torch.empty_like(v)
     ws3 = s3.workspace(1, dev)
+    # about 1 ms per call: 5 warm-up and 5 x reps timed calls, so that the
+    # figure is the steady state (the first calls after a synchronisation
+    # run about 10% slower)
     ms = time_call(lambda: (s3.forward(v, c3, workspace=ws3), s3.inverse(c3, out=o3, workspace=ws3)),
-                   reps)
+                   5 * reps, warmup=5)
     n = s3.R * 128 ** 3
     out["volume_128"] = {"ms_per_step": round(ms, 4), "coefficients_per_s": n / ms * 1e3,
                          "R": s3.R, "hbm_algorithmic_GBps": (2 * 4 * n + 8 * 128 ** 3) / ms / 1e6}

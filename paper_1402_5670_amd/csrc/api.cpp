@@ -277,7 +277,10 @@ int forward3d(const sl_system *s, const float *x, int batch, void *coef, float *
   if (scaled) SL_LAUNCH(P_AUX, st, sl::launch_zero_u32(xmax, batch, st));
   SL_LAUNCH(P_ROWS_REAL_FFT, st, sl::launch_rows_real_fft(vr, x, F, scaled ? xmax : nullptr, batch, st));
   SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, F, F, batch * D, false, st));
-  SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vz, F, F, batch, false, st));
+  // the z pass takes the DFT along z itself, unless F must be divided by
+  // Psi_hat first (the adjoint)
+  const bool zdft = !dual;
+  if (!zdft) SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vz, F, F, batch, false, st));
   if (dual) SL_LAUNCH(P_AUX, st, sl::launch_div_psi(F, s->d_psi, (size_t)s->cfg.npix(), batch, st));
   if (scaled) SL_LAUNCH(P_AUX, st, sl::launch_scales(vr, xmax, scales, batch, st));
   int nb, np;
@@ -286,7 +289,7 @@ int forward3d(const sl_system *s, const float *x, int batch, void *coef, float *
   for (int b0 = 0; b0 < batch; b0 += nb)
     for (int p0 = 0; p0 < P; p0 += np) {
       sl::Chunk c{b0, std::min(nb, batch - b0), p0, std::min(np, P - p0)};
-      SL_LAUNCH(P_COLS_FILTER_IFFT, st, sl::launch_z_filter_ifft(v3, F, T, c, st));
+      SL_LAUNCH(P_COLS_FILTER_IFFT, st, sl::launch_z_filter_ifft(v3, F, T, c, zdft, st));
       if (plane) {
         SL_LAUNCH(P_ROWS_COEF, st, sl::launch_plane_coef(vp, D, T, coef, scales, c, inv_vol, st));
       } else if (half) {
@@ -348,7 +351,6 @@ int denoise_fused_run(const sl_system *s, const float *x_dev, int batch, const s
     const int D = (int)s->cfg.dims[0], H = (int)s->cfg.dims[1], W = (int)s->cfg.dims[2];
     const sl::Sys2D vr = view2d(s, D * H, W, 0, W);
     const sl::Sys2D vy = view2d(s, H, W, H, 0);
-    const sl::Sys2D vz = view2d(s, D, H * W, D, 0);
     const sl::Sys2D vp = view2d(s, H, W, H, W);
     const bool plane = s->plane3d && sl::plane_supported(H, W);
     const sl::Sys3D v3 = view3d(s);
@@ -357,11 +359,10 @@ int denoise_fused_run(const sl_system *s, const float *x_dev, int batch, const s
     else
       SL_LAUNCH(P_ROWS_REAL_FFT, st, sl::launch_rows_real_fft(vr, x_dev, F, nullptr, batch, st));
     SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vy, F, F, batch * D, false, st));
-    SL_LAUNCH(P_COLS_FFT, st, sl::launch_cols_fft(vz, F, F, batch, false, st));
     for (int b0 = 0; b0 < batch; b0 += nb)
       for (int p0 = 0; p0 < P; p0 += np) {
         sl::Chunk c{b0, std::min(nb, batch - b0), p0, std::min(np, P - p0)};
-        SL_LAUNCH(P_COLS_FILTER_IFFT, st, sl::launch_z_filter_ifft(v3, F, T, c, st));
+        SL_LAUNCH(P_COLS_FILTER_IFFT, st, sl::launch_z_filter_ifft(v3, F, T, c, true, st));
         if (plane) {
           SL_LAUNCH(P_ROWS_THR, st, sl::launch_plane_thr(vp, D, T, inv_n, c, thr, st));
         } else {

@@ -160,7 +160,9 @@ struct Sys3D {
   const float2 *twD;
 };
 
-hipError_t launch_z_filter_ifft(const Sys3D &s, const float2 *F, float2 *T, Chunk c,
+// zdft: F carries the x and y transforms only and the kernel takes its DFT
+// along z itself
+hipError_t launch_z_filter_ifft(const Sys3D &s, const float2 *F, float2 *T, Chunk c, bool zdft,
                                 hipStream_t st);
 
 // Plane passes: the y and x line FFTs of each z-slice of a chunk's pair

@@ -78,7 +78,7 @@ template <int N>
 __global__ void __launch_bounds__(Tile3<N>::THREADS)
 k_z_filter_ifft(const float2 *__restrict__ F, const ZPair *__restrict__ pairs,
                 const float2 *__restrict__ tab, float2 *__restrict__ T, int H, int W, int R,
-                int b0, int p0, int np, int split, const float2 *__restrict__ tw) {
+                int b0, int p0, int np, int split, int zdft, const float2 *__restrict__ tw) {
   constexpr int NT = Tile3<N>::NT, M = Tile3<N>::M, E = Tile3<N>::E;
   __shared__ float2 lds[M * N];
   __shared__ float2 twl[N];   // twiddles staged once (ordered by the FFT's leading barrier)
@@ -98,6 +98,9 @@ k_z_filter_ifft(const float2 *__restrict__ F, const ZPair *__restrict__ pairs,
   float2 f[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) f[e] = F[(size_t)b * vol + (size_t)(t + e * NT) * HW + cc];
+  // zdft: F holds the x and y transforms only; its DFT along z is taken here,
+  // once per block, instead of in a pass of its own over the volume
+  if (zdft) fft_line_p<Plan<N>, false>(f, t, LdsLine{lds + m, M}, TwLds{twl});
   float2 cn = q0 < q1 ? (tab + pairs[p0 + q0].c)[y * W + x] : make_float2(0.f, 0.f);
   for (int pp = q0; pp < q1; ++pp) {
     const float2 c = cn;
@@ -122,8 +125,12 @@ k_z_filter_ifft(const float2 *__restrict__ F, const ZPair *__restrict__ pairs,
 // z pass of the inverse transform: DFT along z of each pair's U, multiply by
 // (psi_a - i psi_b), sum over the pairs of the chunk; the last chunk divides
 // by Psi_hat and applies the inverse DFT along z.
+// (128-point lines: at least 4 waves per SIMD, which that instance reaches
+// at 128 VGPRs without spills; the register allocator otherwise settles on
+// 130 and 3 waves depending on what else the file instantiates)
 template <int N>
 __global__ void __launch_bounds__(Tile3<N>::THREADS)
+    __attribute__((amdgpu_waves_per_eu(N == 128 ? 4 : 1)))
 k_z_fft_acc(const float2 *__restrict__ U, const ZPair *__restrict__ pairs,
             const float2 *__restrict__ tab, const float *__restrict__ psi, float2 *__restrict__ ACC,
             int H, int W, int R, int b0, int p0, int np, int first, int last,
@@ -229,7 +236,7 @@ static int z_split(int nblocks, int np, int num_cu) {
   return best;
 }
 
-hipError_t launch_z_filter_ifft(const Sys3D &s, const float2 *F, float2 *T, Chunk c,
+hipError_t launch_z_filter_ifft(const Sys3D &s, const float2 *F, float2 *T, Chunk c, bool zdft,
                                 hipStream_t st) {
   const int HW = s.H * s.W;
   switch (s.D) {
@@ -238,7 +245,8 @@ hipError_t launch_z_filter_ifft(const Sys3D &s, const float2 *F, float2 *T, Chun
     const int tiles = (HW + Tile3<N>::M - 1) / Tile3<N>::M;                                   \
     const int sp = z_split<N>(tiles * c.nb, c.np, s.num_cu);                                  \
     hipLaunchKernelGGL(k_z_filter_ifft<N>, dim3(tiles, c.nb * sp), dim3(Tile3<N>::THREADS), 0, \
-                       st, F, s.pairs, s.tab, T, s.H, s.W, s.R, c.b0, c.p0, c.np, sp, s.twD); \
+                       st, F, s.pairs, s.tab, T, s.H, s.W, s.R, c.b0, c.p0, c.np, sp,         \
+                       (int)zdft, s.twD);                                                     \
     break;                                                                                    \
   }
     SL_FOR_EACH_N(X)
