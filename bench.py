@@ -245,7 +245,7 @@ def other_configs(reps=10):
     o3 = torch.empty_like(v)
     ws3 = s3.workspace(1, dev)
     ms = time_call(lambda: (s3.forward(v, c3, workspace=ws3), s3.inverse(c3, out=o3, workspace=ws3)),
-                   max(2, reps // 2))
+                   max(2, reps // 2), warmup=2)
     n = s3.R * 192 ** 3
     out["video_192"] = {"ms_per_step": round(ms, 4), "coefficients_per_s": n / ms * 1e3,
                         "R": s3.R, "hbm_algorithmic_GBps": (2 * 4 * n + 8 * 192 ** 3) / ms / 1e6,
