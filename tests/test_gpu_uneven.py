@@ -185,12 +185,14 @@ def test_c4_uneven_64_images():
 def test_line_plan_1024(dtype):
     # the second line plan of 1024-point lines (one wavefront per row, 512-thread
     # inverse accumulation blocks) against the default plan and the oracle
-    print(f"case: 1024^2 line plans, B=2, J=2, {dtype}", flush=True)
+    # three images: the two-image column blocks of 1024-point lines get an
+    # odd tail (a block whose second image does not exist)
+    print(f"case: 1024^2 line plans, B=3, J=2, {dtype}", flush=True)
     dims = (1024, 1024)
     s = B.System(dims, 2, [1, 1], dtype=dtype)
-    xs = np.stack([syn.noisy_cartoon2d(*dims, 4200 + b, 0.1)[1] for b in range(2)])
+    xs = np.stack([syn.noisy_cartoon2d(*dims, 4200 + b, 0.1)[1] for b in range(3)])
     xg = torch.from_numpy(xs.astype(np.float32)).to(DEV)
-    sg = torch.tensor([0.1, 0.1], dtype=torch.float32, device=DEV)
+    sg = torch.tensor([0.1, 0.1, 0.1], dtype=torch.float32, device=DEV)
     K = [3.0, 4.0]
     outs = {}
     for em in (1, 2):
@@ -209,8 +211,11 @@ def test_line_plan_1024(dtype):
         assert rel(outs[2][k], outs[1][k]) < tol_gpu, k
     tol = 1e-5 if dtype == "f32" else 2e-3
     o = S.build_2d(dims, 2, [1, 1])
-    assert rel(outs[2][0][0], T.forward(xs[0], o.filters)) < tol
+    for b in (0, 2):
+        for em in (1, 2):
+            assert rel(outs[em][0][b], T.forward(xs[b], o.filters)) < tol, (b, em)
     assert rel(outs[2][1], xs) < tol
+    assert rel(outs[1][1], xs) < tol
 
 
 @pytest.mark.parametrize("dtype", ["f16", "f32"])
