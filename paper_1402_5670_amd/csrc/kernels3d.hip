@@ -125,12 +125,12 @@ k_z_filter_ifft(const float2 *__restrict__ F, const ZPair *__restrict__ pairs,
 // z pass of the inverse transform: DFT along z of each pair's U, multiply by
 // (psi_a - i psi_b), sum over the pairs of the chunk; the last chunk divides
 // by Psi_hat and applies the inverse DFT along z.
-// (128-point lines: at least 4 waves per SIMD, which that instance reaches
-// at 128 VGPRs without spills; the register allocator otherwise settles on
-// 130 and 3 waves depending on what else the file instantiates)
+// (128- and 192-point lines: at least 4 waves per SIMD, which those
+// instances reach at 128 VGPRs (192: 2 spilled); the register allocator
+// otherwise settles on 130 and 3 waves.  192^3: 2.53 -> 2.46 ms per inverse)
 template <int N>
 __global__ void __launch_bounds__(Tile3<N>::THREADS)
-    __attribute__((amdgpu_waves_per_eu(N == 128 ? 4 : 1)))
+    __attribute__((amdgpu_waves_per_eu(N == 128 || N == 192 ? 4 : 1)))
 k_z_fft_acc(const float2 *__restrict__ U, const ZPair *__restrict__ pairs,
             const float2 *__restrict__ tab, const float *__restrict__ psi, float2 *__restrict__ ACC,
             int H, int W, int R, int b0, int p0, int np, int first, int last,
