@@ -1472,6 +1472,8 @@ k_hplane_coef(const float2 *__restrict__ T, typename Store<DT>::T *__restrict__ 
   using HT = HalfTile<H, W>;
   constexpr int HH = HT::HH, NCI = W / HT::MC;
   __shared__ float2 pl[HH * HT::RL];
+  __shared__ float2 twd[HH];   // DIF twiddles w^m (the loop-top barrier orders them)
+  for (int k = threadIdx.x; k < HH; k += HT::THREADS) twd[k] = twH[k];
   const int G = gridDim.x;
   const int nslice = D * np * nb, items = 2 * nslice;
   const size_t slice = (size_t)H * W, vol = slice * D;
@@ -1507,7 +1509,7 @@ k_hplane_coef(const float2 *__restrict__ T, typename Store<DT>::T *__restrict__ 
       float2 v[HT::EC];
 #pragma unroll
       for (int e = 0; e < HT::EC; ++e)
-        v[e] = h ? cmulconj(csub(ca_[e], cc_[e]), twH[tc + e * HT::NTC]) : cadd(ca_[e], cc_[e]);
+        v[e] = h ? cmulconj(csub(ca_[e], cc_[e]), twd[tc + e * HT::NTC]) : cadd(ca_[e], cc_[e]);
       const int x = ci * HT::MC + mc;
       const LdsLine col{pl + x + (x >> 4), HT::RL};
       fft_line_p<typename HT::PC, true>(v, tc, col, TwStep<2>{twH});
