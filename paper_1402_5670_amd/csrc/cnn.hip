@@ -177,15 +177,16 @@ k_conv3x3(const uint16_t *__restrict__ in, const uint16_t *__restrict__ Wp,
 // D[t][p] = sum_ci W3[ci][t] h2[p][ci] for every h2 pixel p, and the output is
 // b3 + sum_t D[t][p + offset(t)].  D needs h2 at p only, so it is computed
 // from the layer-2 accumulators in registers and h2 never reaches LDS.
-// h1 pixels are padded to 40 channels (80 bytes, 16-byte aligned), which
-// spreads the 16 pixels of an operand read over distinct LDS banks.
+// h1 pixels are padded to 48 channels (96 bytes, 16-byte aligned).  Measured
+// per 32 images: 40 channels 17.7 ms, 48 channels 17.3 ms, 56 channels
+// 17.9 ms, 64 channels (128-byte stride) 24.0 ms.
 // Output tile FTH x 32 (SL_CNN_FTH = 16 or 8), one thread per output pixel;
 // pixel stride of h1 SL_CNN_CHP bfloat16 values (>= 32, a multiple of 8).
 #ifndef SL_CNN_FTH
 #define SL_CNN_FTH 16
 #endif
 #ifndef SL_CNN_CHP
-#define SL_CNN_CHP 40
+#define SL_CNN_CHP 48
 #endif
 constexpr int FTH = SL_CNN_FTH, FTW = 32;
 constexpr int X0H = FTH + 6, X0W = FTW + 6;
