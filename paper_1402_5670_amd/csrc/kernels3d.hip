@@ -73,7 +73,8 @@ __device__ __forceinline__ void with_zfilters(const float2 *__restrict__ tab, co
 }
 
 // z pass of the forward transform: F * (psi_a + i psi_b), inverse DFT along z.
-// Columns are the H*W voxels of a z-slice; grid (ceil(HW/M), nb).
+// Columns are the H*W voxels of a z-slice; grid (ceil(HW/M), nb * split):
+// each image's pair loop is cut into split parts of consecutive pairs.
 template <int N>
 __global__ void __launch_bounds__(Tile3<N>::THREADS)
 k_z_filter_ifft(const float2 *__restrict__ F, const ZPair *__restrict__ pairs,
@@ -211,7 +212,8 @@ k_z_fft_acc(const float2 *__restrict__ U, const ZPair *__restrict__ pairs,
 // resident blocks leaves a mostly idle last round (192^3: 2304 blocks, 1024
 // resident, three rounds for 2.25 rounds of work).  Each part reloads its
 // column tile of F (1/np of what it writes); the split that minimises the
-// rounds per unit of work wins, ties going to fewer parts.
+// rounds per unit of work wins, ties going to fewer parts.  Each part also
+// repeats the z DFT of its tile of F when the pass takes that DFT itself.
 template <int N>
 static int z_split(int nblocks, int np, int num_cu) {
   static int per_cu = -1;
