@@ -238,3 +238,36 @@ def test_half_plane_passes(monkeypatch, dims, J, levels, Bn):
                 ct[i] = np.where(np.abs(cg[b, i].astype(np.float32)) >= delta, ct[i], 0.0)
             ref = T.inverse(ct, o.filters, o.dual_weight)
             assert rel(out.cpu().numpy()[b], ref) < 1e-5
+
+
+@pytest.mark.parametrize("dims,J,levels,Bn,plane", [((16, 64, 64), 2, [0, 1], 2, "0"),
+                                                    ((16, 64, 64), 2, [0, 1], 2, "1"),
+                                                    ((8, 192, 128), 1, [0], 1, None)])
+def test_3d_inverse_adjoint(monkeypatch, dims, J, levels, Bn, plane):
+    # adjoint of the dual-frame inverse (used to back-propagate an
+    # image-domain loss): a_i = IDFT(DFT(r) / Psi_hat * psi_hat_i), taken by the
+    # forward path with its z DFT as a pass of its own; line passes, z-slice
+    # planes and half-slice planes.  Against the oracle's filters to 1e-5 and
+    # <inverse(c), r> = <c, adjoint(r)>
+    print(f"case: 3D adjoint {dims} J={J} d={levels} B={Bn} plane={plane}", flush=True)
+    if plane is None:
+        monkeypatch.delenv("SL_PLANE3D", raising=False)
+    else:
+        monkeypatch.setenv("SL_PLANE3D", plane)
+    s = B.System(dims, J, levels)
+    o = S.build_3d(dims, J, levels)
+    assert s.R == o.R
+    rng = np.random.default_rng(63)
+    r = rng.standard_normal((Bn, *dims))
+    c = rng.standard_normal((Bn, s.R, *dims))
+    a = s.inverse_adjoint(_gpu(r))
+    x = s.inverse(_gpu(c))
+    torch.cuda.synchronize()
+    an = a.cpu().numpy().astype(np.float64)
+    for b in range(Bn):
+        Rf = np.fft.fftn(r[b]) / o.dual_weight
+        ref = np.stack([np.fft.ifftn(Rf * f).real for f in o.filters])
+        assert rel(an[b], ref) < 1e-5
+    lhs = np.sum(x.cpu().numpy().astype(np.float64) * r)
+    rhs = np.sum(c * an)
+    assert abs(lhs - rhs) < 1e-5 * np.linalg.norm(c) * np.linalg.norm(an)
