@@ -333,7 +333,8 @@ k_cnn_fused(const float *__restrict__ coef, CnnPlanes pl, int H, int W, int ntil
   auto layers = [&](const FusedTile &f, int buf, auto interior) {
     constexpr bool INTERIOR = decltype(interior)::value != 0;
     // ---- layer 1: NH1 pixels in blocks of 16; wave w takes blocks w, w + NW,
-    // ..., two at a time (independent products and operand reads)
+    // ..., three at a time (independent products and operand reads; 16.6 ->
+    // 16.4 ms per 32 images against two at a time)
     auto l1 = [&](int bA, auto count) {
       constexpr int S = decltype(count)::value;
       bf16x8 xb[S];
@@ -367,8 +368,9 @@ k_cnn_fused(const float *__restrict__ coef, CnnPlanes pl, int H, int W, int ntil
       __builtin_amdgcn_s_setprio(0);
     };
     constexpr int NB1 = NH1 / 16;
-    for (int bA = wave; bA < NB1; bA += 2 * NW) {
-      if (bA + NW < NB1) l1(bA, IntC<2>{});
+    for (int bA = wave; bA < NB1; bA += 3 * NW) {
+      if (bA + 2 * NW < NB1) l1(bA, IntC<3>{});
+      else if (bA + NW < NB1) l1(bA, IntC<2>{});
       else l1(bA, IntC<1>{});
     }
     __syncthreads();
